@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 Galerkin-FFT homogenization hot path on one GPU.
+
+A step is one complete solve of the benchmark workload to the residual tolerance: FP64 right-hand
+side, FP32 MINRES iterations (operator apply = 5 FFT/projection passes + Krylov updates), FP64 true
+residual and refinement, post-processing.  Workload (default): a 256^3 octet-truss RVE at 15%
+relative density with synthetic manufacturing defects (Gaussian-filtered roughness of amplitude
+1.5 voxels, sigma 2 voxels; 200 lognormal pores, median radius 2 voxels), uniaxial macro strain
+eps_11 = 1e-3, isotropic solid E = 1, nu = 0.3, empty phase of zero stiffness, tolerance 1e-6.
+
+Prints one JSON line: voxel-iterations/s (value), wall time per solve (ms_per_step), the roofline
+entry of the dominant kernel (HIP-event durations recorded on the solve stream inside the timed
+solves) and the FP64 CPU checker's rate on a bounded sample of the same problem.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import lattice_inputs as li
+    if name == "octet256_defects":
+        n = (256, 256, 256)
+        phi, info = li.octet_defect_phase_map(n, 0.15)
+        cfg = {"workload": "octet256_defects", "grid": list(n), "rho_target": 0.15, "rho_actual": info.rho_actual,
+               "pores": info.n_pores, "roughness_amp_vox": 1.5, "roughness_sigma_vox": 2.0, "load": "eps11=1e-3",
+               "load_cases": 1, "tol": 1e-6, "precision": "fp32-mixed"}
+        E = li.uniaxial_strain(1e-3)[None]
+    elif name == "octet128_6cases":
+        n = (128, 128, 128)
+        phi, _ = li.octet_phase_map(n, 0.10)
+        cfg = {"workload": "octet128_6cases", "grid": list(n), "rho_target": 0.10,
+               "rho_actual": float(phi.mean(dtype=np.float64)), "load": "6 unit Mandel strains", "load_cases": 6,
+               "tol": 1e-6, "precision": "fp32-mixed"}
+        E = np.eye(6)
+    elif name == "octet32_fp64":
+        n = (32, 32, 32)
+        phi, _ = li.octet_phase_map(n, 0.10)
+        cfg = {"workload": "octet32_fp64", "grid": list(n), "rho_target": 0.10,
+               "rho_actual": float(phi.mean(dtype=np.float64)), "load": "eps11=1e-3", "load_cases": 1,
+               "tol": 1e-8, "precision": "fp64"}
+        E = li.uniaxial_strain(1e-3)[None]
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return n, phi, E, cfg
+
+
+def algorithmic_bytes(kind, n, nc, elem):
+    """Bytes one launch must move (each operand read or written once), FP32/FP64 fields."""
+    n0, n1, n2 = n
+    nv = n0 * n1 * n2
+    spec = 6 * (n2 // 2 + 1) * n0 * n1 * 2 * elem
+    field = 6 * nv * elem
+    table = {
+        "P1_stiffness_fft_axis2": field + 4 * nv + spec,
+        "P2_fft_axis1": 2 * spec,
+        "P3_fft_axis0_projection": 2 * spec,
+        "P4_ifft_axis1": 2 * spec,
+        "P5_ifft_axis2_dot": spec + 2 * field,
+        "U1_lanczos_update": 4 * field,
+        "U2_direction_update": 6 * field,
+    }
+    return table.get(kind, 0) * nc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="octet256_defects")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp32-mixed", "fp64"], default=None,
+                    help="override the workload's precision (fp64 = the plain FP64 GPU MINRES)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build's solver runs on a single MI355X "
+              "(see DESIGN.md for how the path would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2110_00733_amd as rve
+    import lattice_inputs as li
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    t0 = time.time()
+    n, phi, E, cfg = workload(args.workload)
+    if args.precision:
+        cfg["precision"] = args.precision
+    log(f"workload {cfg['workload']} built in {time.time() - t0:.1f}s, rho={cfg['rho_actual']:.5f}")
+    C1 = li.isotropic_mandel(1.0, 0.3)
+    prec = rve.FP64 if cfg["precision"] == "fp64" else rve.FP32_MIXED
+    d = torch.as_tensor(phi, device="cuda:0")
+    ws = rve.Workspace()
+    nvox = int(np.prod(n))
+    nc = E.shape[0]
+
+    def one():
+        return rve.solve(d, C1, E, tol=cfg["tol"], precision=prec, workspace=ws, want_stress=True)
+
+    for i in range(args.warmup):
+        out = one()
+        log(f"warmup {i}: status {out['status']} iters {out['iterations'].tolist()} res {out['rel_residual'].tolist()}")
+    rve.profile_reset()
+    rve.profile_enable(True)
+    torch.cuda.synchronize()
+    times, iters, res = [], [], []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        out = one()
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        times.append(te - ts)
+        iters.append(int(out["iterations"].sum()))
+        res.append(float(out["rel_residual"].max()))
+        log(f"step {i}: {1e3 * (te - ts):.1f} ms, iters {out['iterations'].tolist()}, res {out['rel_residual'].tolist()}")
+    rve.profile_enable(False)
+    prof = rve.profile_read()
+    total_t = sum(times)
+    value = nvox * sum(iters) / total_t
+    ms_per_step = 1e3 * total_t / args.steps
+
+    # roofline entry for the kernel with the largest share of the timed loop
+    elem = 8 if prec == rve.FP64 else 4
+    kernels = {}
+    for k, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        avg = ms / cnt
+        ab = algorithmic_bytes(k, n, nc, elem)
+        kernels[k] = {"total_ms": ms, "launches": cnt, "avg_us": 1e3 * avg, "alg_bytes": ab,
+                      "gbs": (ab / (avg * 1e-3) / 1e9) if ab else None}
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"]) if kernels else None
+    roof = None
+    if dom:
+        kd = kernels[dom]
+        ach = kd["gbs"] or 0.0
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "avg_us": round(kd["avg_us"], 2),
+                "alg_bytes_per_launch": kd["alg_bytes"]}
+    log(json.dumps({k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kernels.items()}))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t1 = time.time()
+        secs = oracle.time_minres(n, phi, C1, iters=args.cpu_iters)
+        cpu = {"value": nvox * args.cpu_iters / secs, "unit": "voxel-iterations/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{args.cpu_iters} FP64 MINRES iteration(s) (operator apply + vector updates) of the CPU "
+                         f"checker on the same {n[0]}x{n[1]}x{n[2]} problem, zero start; {secs:.1f} s"}
+        log(f"cpu baseline {cpu['value']:.3e} voxel-it/s in {time.time() - t1:.1f}s wall")
+
+    cfg.update({"iterations_per_solve": iters[-1] // nc if nc else 0, "rel_residual": max(res),
+                "wall_time_to_tol_ms": round(ms_per_step, 2), "minres_iterations_per_s": sum(iters) / total_t / nc,
+                "parallelism": "single-gpu"})
+    line = {"metric": "voxel-iterations/s + wall time to 1e-6 residual at 256^3, learned vs plain",
+            "value": value, "unit": "voxel-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if prec == rve.FP64 else "f32", "data": "synthetic", "config": cfg,
+            "roofline": roof, "cpu_baseline": cpu, "kernels": kernels}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,140 @@
+/*
+ * rve.h - C ABI of the MI355X (gfx950) Galerkin-FFT homogenization solver for lattice materials
+ * with empty (zero-stiffness) phases.
+ *
+ * Method (paper: "Adaptation and validation of FFT methods for homogenization of lattice based
+ * materials", section "Galerkin-FFT with discrete differences and mixed loading control"):
+ * find the periodic, compatible, zero-mean strain fluctuation eps on a regular voxel grid such that
+ *     F^{-1}{ Ghat(xi') : F{ C(x) : eps } } = - F^{-1}{ Ghat(xi') : F{ C(x) : Ebar } }     (eq. gallin)
+ * with C(x) = phi(x) C_solid + (1 - phi(x)) C_void (Voigt rule, section "Voigt approaches"), the
+ * projection Ghat of eq. (galop) under pure strain control, the rotated forward-difference modified
+ * frequencies xi' of eq. (freqrot), and MINRES as the Krylov solver; convergence is tested on the
+ * relative residual of eq. (galres).
+ *
+ * Conventions used by every entry point
+ *   - grid: n[0] x n[1] x n[2] voxels, axis 2 contiguous; voxel sizes h_p = L[p] / n[p].
+ *   - tensors are Mandel 6-vectors (11, 22, 33, sqrt2*23, sqrt2*13, sqrt2*12); the Euclidean dot
+ *     product of two Mandel vectors is the Frobenius product of the tensors.
+ *   - fields are component-major: field[case][component][i0][i1][i2].
+ *   - "device" pointers are HIP device memory on the current device; "host" pointers are host memory.
+ *   - the caller owns every buffer.  The library keeps no pointer after a call returns and never
+ *     allocates device memory: all scratch comes from the caller's workspace.
+ *   - calls run on the given HIP stream (NULL = default stream); host outputs are written and the
+ *     stream is synchronised before the call returns.
+ *   - argument validation happens on the host before any HIP call; a rejected call touches no
+ *     device state.
+ */
+#ifndef RVE_H
+#define RVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RVE_OK = 0,
+  RVE_NOT_CONVERGED = 1,     /* max_iter reached; outputs hold the last iterate */
+  RVE_BREAKDOWN = 2,         /* MINRES rotation with zero norm (inconsistent singular system) */
+  RVE_EINVAL = -1,           /* bad argument (null pointer, non-finite or out-of-range value) */
+  RVE_EUNSUPPORTED_SIZE = -2,/* a grid length the FFT kernels do not provide */
+  RVE_ENONFINITE = -3,       /* non-finite input or a non-finite Krylov scalar during the solve */
+  RVE_ENOMEM = -4,           /* workspace smaller than rve_workspace_bytes() */
+  RVE_EDEVICE = -5           /* a HIP runtime error */
+} rve_status;
+
+enum { RVE_FP32_MIXED = 0, RVE_FP64 = 1 };
+enum { RVE_SCHEME_ROTATED = 0, RVE_SCHEME_CONTINUOUS = 1 };
+enum { RVE_NYQ_NATURAL = 0, RVE_NYQ_ZERO_ALL = 1 };
+enum { RVE_APPLY_OPERATOR = 0, RVE_APPLY_PROJECTION = 1, RVE_APPLY_STIFFNESS_ROUNDTRIP = 2 };
+
+typedef struct {
+  int32_t n[3]; /* voxels per axis, each a length rve_supported_length() accepts */
+  double L[3];  /* cell edge lengths (> 0) */
+} rve_grid;
+
+typedef struct {
+  double tol;           /* relative residual target ||A eps - b|| / ||b||  (eq. galres), > 0 */
+  int32_t max_iter;     /* MINRES iterations cap per load case (summed over refinement sweeps) */
+  int32_t precision;    /* RVE_FP32_MIXED: FP32 fields and transforms, FP64 scalars, inner products,
+                           true residual and refinement;  RVE_FP64: everything FP64 */
+  int32_t max_refine;   /* FP32_MIXED: maximum FP64 residual-refinement sweeps (>= 1) */
+  int32_t nyquist;      /* RVE_NYQ_NATURAL (default): the projection vanishes only where the
+                           modified frequency vanishes; RVE_NYQ_ZERO_ALL: also at every Nyquist index */
+  int32_t scheme;       /* RVE_SCHEME_ROTATED (eq. freqrot, default) or RVE_SCHEME_CONTINUOUS (eq. freq) */
+  int32_t check_every;  /* iterations between host checks of the convergence flags (>= 1) */
+  double inner_floor;   /* FP32_MIXED: an inner FP32 sweep stops no later than at this fraction of its
+                           own starting residual (default 1e-5; in (0, 1)) */
+  double inner_safety;  /* FP32_MIXED: an inner sweep aims at inner_safety * tol * ||b|| (default 0.5) */
+} rve_options;
+
+/* Fills *opt with the defaults: tol 1e-6, max_iter 5000, FP32_MIXED, max_refine 4, natural Nyquist,
+ * rotated scheme, check_every 24, inner_floor 1e-5, inner_safety 0.5. */
+void rve_default_options(rve_options* opt);
+
+/* 1 if the FFT kernels provide axis length n (n = NA*NB with radix factors 2, 3, 4, 5), else 0. */
+int32_t rve_supported_length(int32_t n);
+
+/* Host-side validation of a solve_rve call's scalar arguments (no HIP call, no pointer dereference
+ * of device buffers).  Returns RVE_OK or the error solve_rve would return. */
+rve_status rve_validate(const rve_grid* grid, const double* phase_stiffness, const double* macro_strain,
+                        int32_t n_cases, const rve_options* opt);
+
+/* Workspace bytes solve_rve needs for this grid, number of load cases and options (0 on bad input). */
+size_t rve_workspace_bytes(const rve_grid* grid, int32_t n_cases, const rve_options* opt);
+
+/* Galerkin-FFT homogenization of one RVE under n_cases macro strains (eq. gallin, strain control).
+ *   voxel_fraction_field  device float [N]: solid fraction phi in [0,1] of each voxel (Voigt rule)
+ *   phase_stiffness       host double [2][36]: Mandel 6x6 stiffness of the empty phase ([0], usually
+ *                         all zero) and of the solid ([1]); each must be symmetric and finite
+ *   macro_strain          host double [n_cases][6]: Mandel macro strains Ebar
+ *   eps0                  device [n_cases][6][N] warm start (float for FP32_MIXED, double for FP64) or
+ *                         NULL for the zero start; it is projected onto compatible fields first
+ *   strain_out            device [n_cases][6][N] (float / double): the fluctuation eps (total = Ebar+eps)
+ *   stress_out            device [n_cases][6][N] (float / double) or NULL: sigma = C(x)(Ebar + eps)
+ *   eff_stress            host double [n_cases][6]: volume average <sigma> (FP64); for unit Mandel
+ *                         macro strains e_J this is column J of the effective stiffness
+ *   iterations            host int32 [n_cases]: MINRES iterations (operator applications in the loop)
+ *   rel_residual          host double [n_cases]: ||b - A eps|| / ||b|| recomputed in FP64 at exit
+ * Returns the worst status over the load cases. */
+rve_status solve_rve(const rve_grid* grid, const float* voxel_fraction_field, const double* phase_stiffness,
+                     const double* macro_strain, int32_t n_cases, const rve_options* opt, const void* eps0,
+                     void* strain_out, void* stress_out, double* eff_stress, int32_t* iterations,
+                     double* rel_residual, void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Workspace bytes rve_apply needs. */
+size_t rve_apply_workspace_bytes(const rve_grid* grid, int32_t n_cases, int32_t precision);
+
+/* One application of the Galerkin operator pieces to n_cases fields (eq. linearOp):
+ *   mode RVE_APPLY_OPERATOR:            y = F^{-1}{ Ghat : F{ C(x) : x } }
+ *   mode RVE_APPLY_PROJECTION:          y = F^{-1}{ Ghat : F{ x } }       (C = identity)
+ *   mode RVE_APPLY_STIFFNESS_ROUNDTRIP: y = F^{-1}{ F{ C(x) : x } }       (Ghat = identity)
+ * x, y: device [n_cases][6][N] float (precision RVE_FP32_MIXED) or double (RVE_FP64); phase_stiffness
+ * as in solve_rve (ignored for PROJECTION). */
+rve_status rve_apply(const rve_grid* grid, const float* voxel_fraction_field, const double* phase_stiffness,
+                     int32_t n_cases, int32_t precision, int32_t scheme, int32_t nyquist, int32_t mode,
+                     const void* x, void* y, void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Optional per-kernel timing (instrumentation for benchmarks, not on by default).  When enabled,
+ * every kernel launched inside the MINRES iteration loop of solve_rve is bracketed by HIP events
+ * recorded on the solve stream; elapsed times are accumulated per kernel kind at the host's
+ * convergence checks.  Kinds, in order: P1 stiffness + FFT axis 2, P2 FFT axis 1, P3 FFT axis 0 +
+ * projection + inverse, P4 inverse FFT axis 1, P5 inverse FFT axis 2 + dot partials, S1 Lanczos
+ * alpha, U1 Lanczos update, S2 Givens step, U2 direction + solution update.
+ * rve_profile_read fills total milliseconds and launch counts for up to max_kinds kinds and
+ * returns the number of kinds.  Not thread-safe with concurrent solves. */
+void rve_profile_enable(int32_t on);
+void rve_profile_reset(void);
+int32_t rve_profile_read(double* total_ms, int64_t* launches, int32_t max_kinds);
+const char* rve_profile_kind_name(int32_t kind);
+
+/* Human-readable name of a status code (static string). */
+const char* rve_status_string(rve_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RVE_H */

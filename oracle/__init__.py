@@ -55,6 +55,8 @@ def _load():
         lib.or_solve.argtypes = [ip, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
                                  ctypes.c_int, dp, dp, dp, dp, dp, dp]
         lib.or_num_threads.restype = ctypes.c_int
+        lib.or_time_minres.argtypes = [ip, dp, dp, dp, dp, ctypes.c_int]
+        lib.or_time_minres.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -207,6 +209,17 @@ def solve(n, phi, C1, Ebar, tol=1e-8, maxit=1000, C0=None, L=(1.0, 1.0, 1.0), sc
                 sigma_mean=tensor_to_mandel(smean), iterations=it, status=int(info[1]),
                 rel_residual=float(info[2]), true_residual=float(info[3]), bnorm=float(info[4]),
                 history=hist[:it].copy())
+
+
+def time_minres(n, phi, C1, iters=1, C0=None, L=(1.0, 1.0, 1.0)) -> float:
+    """Wall seconds of `iters` MINRES iterations (operator + vector work) on this problem."""
+    n = _n3(n)
+    N = int(np.prod(n))
+    phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(N)
+    C1 = np.ascontiguousarray(C1, dtype=np.float64).reshape(36)
+    C0 = np.zeros(36) if C0 is None else np.ascontiguousarray(C0, dtype=np.float64).reshape(36)
+    return float(_load().or_time_minres((ctypes.c_int * 3)(*n), _dp(np.asarray(L, dtype=np.float64)), _dp(phi),
+                                        _dp(C1), _dp(C0), int(iters)))
 
 
 def effective_stiffness(n, phi, C1, tol=1e-10, maxit=5000, cases=range(6), **kw) -> tuple[np.ndarray, list]:

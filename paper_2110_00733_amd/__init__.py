@@ -1,0 +1,255 @@
+"""Python binding of librve.so, the gfx950 Galerkin-FFT homogenization solver (C ABI in include/rve.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP kernels.  PyTorch
+supplies device memory (workspace, fields) and the current HIP stream.  There is no CPU fallback:
+importing works without a GPU (so the ABI can be inspected), but any solve or apply needs the built
+library and a ROCm device, and raises otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librve.so")
+
+RVE_OK, RVE_NOT_CONVERGED, RVE_BREAKDOWN = 0, 1, 2
+RVE_EINVAL, RVE_EUNSUPPORTED_SIZE, RVE_ENONFINITE, RVE_ENOMEM, RVE_EDEVICE = -1, -2, -3, -4, -5
+FP32_MIXED, FP64 = 0, 1
+ROTATED, CONTINUOUS = 0, 1
+NYQ_NATURAL, NYQ_ZERO_ALL = 0, 1
+APPLY_OPERATOR, APPLY_PROJECTION, APPLY_STIFFNESS_ROUNDTRIP = 0, 1, 2
+
+# every symbol include/rve.h declares
+ABI_SYMBOLS = ("rve_default_options", "rve_supported_length", "rve_validate", "rve_workspace_bytes", "solve_rve",
+               "rve_apply_workspace_bytes", "rve_apply", "rve_profile_enable", "rve_profile_reset", "rve_profile_read",
+               "rve_profile_kind_name", "rve_status_string")
+
+
+class RveError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("L", ctypes.c_double * 3)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32), ("nyquist", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("inner_floor", ctypes.c_double), ("inner_safety", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load librve.so (fails loudly if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2110_00733_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+    gp, op = ctypes.POINTER(Grid), ctypes.POINTER(Options)
+    lib.rve_default_options.argtypes = [op]
+    lib.rve_default_options.restype = None
+    lib.rve_supported_length.argtypes = [ctypes.c_int32]
+    lib.rve_supported_length.restype = ctypes.c_int32
+    lib.rve_validate.argtypes = [gp, dp, dp, ctypes.c_int32, op]
+    lib.rve_validate.restype = ctypes.c_int
+    lib.rve_workspace_bytes.argtypes = [gp, ctypes.c_int32, op]
+    lib.rve_workspace_bytes.restype = ctypes.c_size_t
+    lib.solve_rve.argtypes = [gp, vp, dp, dp, ctypes.c_int32, op, vp, vp, vp, dp, ip, dp, vp, ctypes.c_size_t, vp]
+    lib.solve_rve.restype = ctypes.c_int
+    lib.rve_apply_workspace_bytes.argtypes = [gp, ctypes.c_int32, ctypes.c_int32]
+    lib.rve_apply_workspace_bytes.restype = ctypes.c_size_t
+    lib.rve_apply.argtypes = [gp, vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.c_int32, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.rve_apply.restype = ctypes.c_int
+    lib.rve_profile_enable.argtypes = [ctypes.c_int32]
+    lib.rve_profile_enable.restype = None
+    lib.rve_profile_reset.argtypes = []
+    lib.rve_profile_reset.restype = None
+    lib.rve_profile_read.argtypes = [dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    lib.rve_profile_read.restype = ctypes.c_int32
+    lib.rve_profile_kind_name.argtypes = [ctypes.c_int32]
+    lib.rve_profile_kind_name.restype = ctypes.c_char_p
+    lib.rve_status_string.argtypes = [ctypes.c_int]
+    lib.rve_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def profile_enable(on: bool = True) -> None:
+    load_library().rve_profile_enable(1 if on else 0)
+
+
+def profile_reset() -> None:
+    load_library().rve_profile_reset()
+
+
+def profile_read() -> dict:
+    """{kernel kind: (total ms, launches)} accumulated since the last reset."""
+    lib = load_library()
+    ms = np.zeros(16)
+    cnt = np.zeros(16, dtype=np.int64)
+    k = lib.rve_profile_read(_dp(ms), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 16)
+    return {lib.rve_profile_kind_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}
+
+
+def status_string(s: int) -> str:
+    return load_library().rve_status_string(int(s)).decode()
+
+
+def make_grid(n, L=(1.0, 1.0, 1.0)) -> Grid:
+    if isinstance(n, int):
+        n = (n, n, n)
+    g = Grid()
+    g.n[:] = tuple(int(v) for v in n)
+    g.L[:] = tuple(float(v) for v in L)
+    return g
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load_library().rve_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def supported_length(n: int) -> bool:
+    return bool(load_library().rve_supported_length(int(n)))
+
+
+def _stiffness(C_solid, C_void=None) -> np.ndarray:
+    C = np.zeros((2, 6, 6))
+    if C_void is not None:
+        C[0] = np.asarray(C_void, dtype=np.float64)
+    C[1] = np.asarray(C_solid, dtype=np.float64)
+    return np.ascontiguousarray(C.reshape(72))
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def validate(n, C_solid, macro_strain, opt: Options | None = None, C_void=None, L=(1.0, 1.0, 1.0)) -> int:
+    """Host-side argument check (no GPU needed)."""
+    g = make_grid(n, L)
+    C = _stiffness(C_solid, C_void)
+    E = np.ascontiguousarray(np.asarray(macro_strain, dtype=np.float64).reshape(-1, 6))
+    opt = opt or default_options()
+    return int(load_library().rve_validate(ctypes.byref(g), _dp(C), _dp(E), E.shape[0], ctypes.byref(opt)))
+
+
+def workspace_bytes(n, n_cases: int, opt: Options | None = None, L=(1.0, 1.0, 1.0)) -> int:
+    g = make_grid(n, L)
+    return int(load_library().rve_workspace_bytes(ctypes.byref(g), int(n_cases), ctypes.byref(opt or default_options())))
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no ROCm GPU visible: the solver has no CPU path")
+    return torch
+
+
+def _stream_ptr(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Workspace:
+    """Reusable device workspace (a torch uint8 buffer), grown on demand."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device):
+        torch = _torch()
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = None
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_default_ws = Workspace()
+
+
+def solve(phi, C_solid, macro_strain, *, C_void=None, L=(1.0, 1.0, 1.0), opt: Options | None = None, eps0=None,
+          want_stress: bool = True, workspace: Workspace | None = None, check: bool = True, **opt_kw) -> dict:
+    """solve_rve on a device phase map `phi` (torch float32 [n0,n1,n2]) for each macro strain row.
+
+    Returns dict(strain [nc,6,*n], stress [nc,6,*n] or None, eff_stress [nc,6], iterations [nc],
+    rel_residual [nc], status)."""
+    torch = _torch()
+    lib = load_library()
+    if not (phi.is_cuda and phi.dtype == torch.float32 and phi.dim() == 3 and phi.is_contiguous()):
+        raise ValueError("phi must be a contiguous float32 CUDA tensor of shape (n0, n1, n2)")
+    n = tuple(phi.shape)
+    opt = opt or default_options(**opt_kw)
+    E = np.ascontiguousarray(np.asarray(macro_strain, dtype=np.float64).reshape(-1, 6))
+    nc = E.shape[0]
+    C = _stiffness(C_solid, C_void)
+    g = make_grid(n, L)
+    fdt = torch.float32 if opt.precision == FP32_MIXED else torch.float64
+    strain = torch.empty((nc, 6) + n, dtype=fdt, device=phi.device)
+    stress = torch.empty((nc, 6) + n, dtype=fdt, device=phi.device) if want_stress else None
+    if eps0 is not None:
+        eps0 = eps0.to(device=phi.device, dtype=fdt).contiguous()
+        if tuple(eps0.shape) != (nc, 6) + n:
+            raise ValueError("eps0 must have shape (n_cases, 6, n0, n1, n2)")
+    nbytes = lib.rve_workspace_bytes(ctypes.byref(g), nc, ctypes.byref(opt))
+    if nbytes == 0:
+        s = lib.rve_validate(ctypes.byref(g), _dp(C), _dp(E), nc, ctypes.byref(opt))
+        raise RveError(s if s != 0 else RVE_EINVAL, "rve_workspace_bytes")
+    ws = (workspace or _default_ws).get(nbytes, phi.device)
+    eff = np.zeros((nc, 6))
+    its = np.zeros(nc, dtype=np.int32)
+    res = np.zeros(nc)
+    st = lib.solve_rve(ctypes.byref(g), ctypes.c_void_p(phi.data_ptr()), _dp(C), _dp(E), nc, ctypes.byref(opt),
+                       ctypes.c_void_p(eps0.data_ptr()) if eps0 is not None else None,
+                       ctypes.c_void_p(strain.data_ptr()),
+                       ctypes.c_void_p(stress.data_ptr()) if stress is not None else None,
+                       _dp(eff), its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(res),
+                       ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), _stream_ptr(torch, phi.device))
+    if check and st < 0:
+        raise RveError(st, "solve_rve")
+    return dict(strain=strain, stress=stress, eff_stress=eff, iterations=its, rel_residual=res, status=int(st))
+
+
+def apply(x, phi=None, C_solid=None, *, C_void=None, mode: int = APPLY_OPERATOR, L=(1.0, 1.0, 1.0),
+          scheme: int = ROTATED, nyquist: int = NYQ_NATURAL, workspace: Workspace | None = None):
+    """rve_apply on fields x (torch [nc,6,n0,n1,n2], float32 -> FP32 kernels, float64 -> FP64 kernels)."""
+    torch = _torch()
+    lib = load_library()
+    if not (x.is_cuda and x.dim() == 5 and x.shape[1] == 6 and x.is_contiguous()):
+        raise ValueError("x must be a contiguous CUDA tensor of shape (n_cases, 6, n0, n1, n2)")
+    prec = FP32_MIXED if x.dtype == torch.float32 else FP64
+    if x.dtype not in (torch.float32, torch.float64):
+        raise ValueError("x must be float32 or float64")
+    n = tuple(x.shape[2:])
+    nc = x.shape[0]
+    g = make_grid(n, L)
+    C = _stiffness(C_solid if C_solid is not None else np.eye(6), C_void)
+    y = torch.empty_like(x)
+    nbytes = lib.rve_apply_workspace_bytes(ctypes.byref(g), nc, prec)
+    if nbytes == 0:
+        raise RveError(RVE_EUNSUPPORTED_SIZE if not all(supported_length(v) for v in n) else RVE_EINVAL,
+                       "rve_apply_workspace_bytes")
+    ws = (workspace or _default_ws).get(nbytes, x.device)
+    phip = ctypes.c_void_p(phi.data_ptr()) if phi is not None else None
+    st = lib.rve_apply(ctypes.byref(g), phip, _dp(C), nc, prec, scheme, nyquist, mode, ctypes.c_void_p(x.data_ptr()),
+                       ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                       _stream_ptr(torch, x.device))
+    if st != RVE_OK:
+        raise RveError(st, "rve_apply")
+    return y

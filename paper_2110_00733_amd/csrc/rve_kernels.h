@@ -1,0 +1,439 @@
+// HIP pass kernels of the Galerkin operator A(e) = F^{-1}{ Ghat : F{ C(x) : e } } for gfx950.
+//
+// Data layout (per load case):
+//   real fields   [6][N0][N1][N2]        Mandel components (11,22,33,sqrt2*23,sqrt2*13,sqrt2*12), axis 2 contiguous
+//   half spectrum [K2][6][N0][N1] complex, K2 = N2/2 + 1 (plane-major: axis 1 contiguous)
+// One operator application is five passes, each one streaming read + write over HBM:
+//   P1 k_fwd_axis2     stiffness sigma = C(x) e (Voigt rule) fused into the real-to-complex FFT along axis 2;
+//                      two real components are packed into one complex transform and separated after it;
+//                      output written transposed into the plane-major half spectrum
+//   P2 k_axis1<-1>     complex FFT along axis 1 (contiguous rows)
+//   P3 k_axis0_project FFT along axis 0, per-frequency Galerkin projection (eq. galop with the rotated
+//                      modified frequencies of eq. freqrot), inverse FFT along axis 0 - all 6 components of a
+//                      pencil meet in registers here
+//   P4 k_axis1<+1>     inverse FFT along axis 1
+//   P5 k_inv_axis2     complex-to-real inverse FFT along axis 2 back to [6][N0][N1][N2], fused with the
+//                      per-block FP64 partial of <A v, v> used by MINRES
+// Every 1-D transform of length N = NA*NB runs as two register-resident small DFTs (radix NA, then NB)
+// with one LDS exchange between them.  Each thread owns one stage-A column t in [0,NB).
+#pragma once
+#include "rve_device.h"
+
+namespace rve {
+
+struct GridDims {
+  int n0, n1, n2, k2;      // k2 = n2/2 + 1
+  long long nvox;          // n0*n1*n2
+  long long spec_case;     // 6*k2*n0*n1 complex elements per load case
+};
+
+// Per-solve MINRES scalars (FP64), one per load case, resident on the device.
+struct MinresState {
+  double beta, ib, ib_prev;          // beta_k, 1/beta_k, 1/beta_{k-1} (deferred normalisation of v)
+  double alpha;                      // Lanczos diagonal
+  double c1, s1, c2, s2;             // Givens rotations G_{k-1}, G_{k-2}
+  double phibar;                     // |phibar| = residual norm of the current iterate
+  double tol_abs;                    // stop when |phibar| <= tol_abs
+  double cu_v, cu_vp;                // Lanczos update coefficients (on raw u_k, u_{k-1})
+  double cd_u, cd_d1, cd_d2, cx;     // search-direction / solution update coefficients
+  double sumsq;                      // scratch: last reduced sum
+  int iter, max_iter, finish, done, status, pad;
+};
+
+template <typename T>
+struct Material {
+  T C0[36];  // stiffness of the empty phase (normally zero)
+  T Cd[36];  // C_solid - C_void:  C(x) = C0 + phi(x) Cd  (Voigt rule)
+  int has_c0;
+  int use_phi;  // 0: C(x) = C0 everywhere (phi is not read)
+};
+
+template <typename T>
+struct FreqTables {
+  const T* s[3];  // sin(q/2)/h (rotated scheme) per axis and storage index
+  const T* c[3];  // cos(q/2), exact 0 at a Nyquist index
+};
+
+__device__ __forceinline__ long long spec_idx(const GridDims& g, int cs, int k2, int c, int n0, int n1) {
+  return ((((long long)cs * g.k2 + k2) * 6 + c) * g.n0 + n0) * (long long)g.n1 + n1;
+}
+
+// ============================================================================ P1
+// grid (ceil(N1/W), N0, ncases), block W*NB threads, dyn. LDS W*max(NA*(NB+1), N+1) complex
+template <typename T, int NA, int NB>
+__global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib, int xscale_stride,
+                            const float* __restrict__ phi, Material<T> mat, cx<T>* __restrict__ spec,
+                            const cx<T>* __restrict__ tw, GridDims g, int W, const MinresState* __restrict__ st) {
+  constexpr int N = NA * NB;
+  constexpr int TT = NB;
+  constexpr int CB = (NA + TT - 1) / TT;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int cs = blockIdx.z;
+  if (st && st[cs].finish) return;
+  const int n0 = blockIdx.y;
+  const int n1_0 = blockIdx.x * W;
+  const int tid = threadIdx.x;
+  const int t = tid % TT, w = tid / TT;
+  const int n1 = n1_0 + w;
+  const bool row_ok = n1 < g.n1;
+  const T xs = xscale_ib ? (T)xscale_ib[(long long)cs * xscale_stride] : (T)1;
+  const long long row = ((long long)n0 * g.n1 + n1) * N;
+  const T* xc = x + (long long)cs * 6 * g.nvox;
+
+  T sg[6][NA];
+  {
+    T e[6][NA], ph[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      ph[i] = (row_ok && mat.use_phi) ? (T)phi[row + t + NB * i] : (T)0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) e[c][i] = row_ok ? xc[c * g.nvox + row + t + NB * i] : (T)0;
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        T acc = 0;
+        if (mat.use_phi) {
+#pragma unroll
+          for (int b = 0; b < 6; ++b) acc += mat.Cd[a * 6 + b] * e[b][i];
+          acc *= ph[i];
+        }
+        if (mat.has_c0) {
+#pragma unroll
+          for (int b = 0; b < 6; ++b) acc += mat.C0[a * 6 + b] * e[b][i];
+        }
+        sg[a][i] = acc * xs;
+      }
+    }
+  }
+  const int ws = tid % W, m = tid / W, M = blockDim.x / W;
+  const int n1s = n1_0 + ws;
+#pragma unroll
+  for (int pr = 0; pr < 3; ++pr) {
+    cx<T> z[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) z[i] = mk<T>(sg[2 * pr][i], sg[2 * pr + 1][i]);
+    DFT<NA, -1, T>::run(z);
+#pragma unroll
+    for (int a = 1; a < NA; ++a) z[a] = cmul(z[a], tw[(t * a) % N]);
+    lds_barrier();
+#pragma unroll
+    for (int a = 0; a < NA; ++a) lds[(w * NA + a) * (NB + 1) + t] = z[a];
+    lds_barrier();
+    cx<T> yb[CB][NB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) yb[j][u] = lds[(w * NA + a) * (NB + 1) + u];
+        DFT<NB, -1, T>::run(yb[j]);
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) lds[w * (N + 1) + a + NA * b] = yb[j][b];
+      }
+    }
+    lds_barrier();
+    if (n1s < g.n1) {
+      for (int k = m; k < g.k2; k += M) {
+        const cx<T> Z = lds[ws * (N + 1) + k];
+        const cx<T> Zm = lds[ws * (N + 1) + (N - k) % N];
+        const cx<T> A = mk<T>((Z.re + Zm.re) * (T)0.5, (Z.im - Zm.im) * (T)0.5);
+        const cx<T> B = mk<T>((Z.im + Zm.im) * (T)0.5, (Zm.re - Z.re) * (T)0.5);
+        spec[spec_idx(g, cs, k, 2 * pr, n0, n1s)] = A;
+        spec[spec_idx(g, cs, k, 2 * pr + 1, n0, n1s)] = B;
+      }
+    }
+  }
+}
+
+// ============================================================================ P2 / P4
+// rows of N1 complex, contiguous; grid (ceil(rows/R)), block R*NB threads
+template <typename T, int NA, int NB, int S>
+__global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, GridDims g, int R,
+                        long long total_rows, const MinresState* __restrict__ st) {
+  constexpr int N = NA * NB;
+  constexpr int TT = NB;
+  constexpr int CB = (NA + TT - 1) / TT;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int t = tid % TT, w = tid / TT;
+  const long long rows_per_case = (long long)g.k2 * 6 * g.n0;
+  const long long row = (long long)blockIdx.x * R + w;
+  const int cs = (int)(row / rows_per_case);
+  const bool ok = (row < total_rows) && !(st && st[cs].finish);
+  cx<T>* rp = spec + row * N;
+  cx<T> z[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) z[i] = ok ? rp[t + NB * i] : mk<T>(0, 0);
+  DFT<NA, S, T>::run(z);
+#pragma unroll
+  for (int a = 1; a < NA; ++a) z[a] = (S < 0) ? cmul(z[a], tw[(t * a) % N]) : cmulc(z[a], tw[(t * a) % N]);
+#pragma unroll
+  for (int a = 0; a < NA; ++a) lds[(w * NA + a) * (NB + 1) + t] = z[a];
+  lds_barrier();
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int a = t + TT * j;
+    if (a < NA) {
+      cx<T> yb[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) yb[u] = lds[(w * NA + a) * (NB + 1) + u];
+      DFT<NB, S, T>::run(yb);
+      if (ok) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) rp[a + NA * b] = yb[b];
+      }
+    }
+  }
+}
+
+// ============================================================================ P3
+// grid (ceil(N1/W), K2, ncases), block W*NB threads, dyn. LDS NA*(NB*W+1) complex
+// All six components of the thread's pencil elements are loaded up front (maximum loads in flight)
+// and transformed in place in one register array D[c][.]: stage-A layout D[c][i] = x[t + NB i],
+// stage-B layout D[c][j*NB + b] = X[a_j + NA b] with a_j = t + NB j.
+template <typename T, int NA, int NB>
+__global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw,
+                                                       FreqTables<T> ft, GridDims g, int W, T inv_total, int identity,
+                                                       const MinresState* __restrict__ st) {
+  constexpr int N = NA * NB;
+  constexpr int TT = NB;
+  constexpr int CB = (NA + TT - 1) / TT;
+  constexpr int E = (NA > CB * NB) ? NA : CB * NB;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int cs = blockIdx.z;
+  if (st && st[cs].finish) return;
+  const int k2 = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int w = tid % W, t = tid / W;
+  const int k1 = blockIdx.x * W + w;
+  const bool ok = k1 < g.n1;
+  const int RS = NB * W + 1;
+  const long long pstride = (long long)g.n0 * g.n1;  // component stride inside one k2 plane
+  cx<T>* base = spec + spec_idx(g, cs, k2, 0, 0, ok ? k1 : 0);
+
+  cx<T> D[6][E];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) D[c][i] = ok ? base[c * pstride + (long long)(t + NB * i) * g.n1] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    DFT<NA, -1, T>::run(D[c]);
+#pragma unroll
+    for (int a = 1; a < NA; ++a) D[c][a] = cmul(D[c][a], tw[(t * a) % N]);
+    lds_barrier();
+#pragma unroll
+    for (int a = 0; a < NA; ++a) lds[a * RS + t * W + w] = D[c][a];
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) D[c][j * NB + u] = lds[a * RS + u * W + w];
+        DFT<NB, -1, T>::run(&D[c][j * NB]);
+      }
+    }
+  }
+
+  // ---- per-frequency projection: Ghat S = t (x) n + n (x) t - (n.t) n (x) n, n = w/|w|
+  const T sq2 = (T)1.41421356237309504880168872420970, isq2 = (T)0.70710678118654752440084436210485;
+  const int k1c = ok ? k1 : 0;
+  const T s1 = ft.s[1][k1c], c1 = ft.c[1][k1c], s2 = ft.s[2][k2], c2 = ft.c[2][k2];
+  const T c1c2 = c1 * c2, s1c2 = s1 * c2, c1s2 = c1 * s2;
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int a = t + TT * j;
+    if (a < NA) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int e = j * NB + b;
+        const int k0 = a + NA * b;
+        if (identity) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) D[c][e] = scl(D[c][e], inv_total);
+        } else {
+          const T s0 = ft.s[0][k0], c0 = ft.c[0][k0];
+          const T w0 = s0 * c1c2, w1 = c0 * s1c2, w2 = c0 * c1s2;
+          const T nn = w0 * w0 + w1 * w1 + w2 * w2;
+          if (nn > (T)0) {
+            const T inv = (T)1 / sqrt(nn);
+            const T m0 = w0 * inv, m1 = w1 * inv, m2 = w2 * inv;
+            const cx<T> S00 = D[0][e], S11 = D[1][e], S22 = D[2][e];
+            const cx<T> S12 = scl(D[3][e], isq2), S02 = scl(D[4][e], isq2), S01 = scl(D[5][e], isq2);
+            const cx<T> t0 = scl(S00, m0) + scl(S01, m1) + scl(S02, m2);
+            const cx<T> t1 = scl(S01, m0) + scl(S11, m1) + scl(S12, m2);
+            const cx<T> t2 = scl(S02, m0) + scl(S12, m1) + scl(S22, m2);
+            const cx<T> q = scl(t0, m0) + scl(t1, m1) + scl(t2, m2);
+            const T f = inv_total, fs = inv_total * sq2;
+            D[0][e] = scl(scl(t0, (T)2 * m0) - scl(q, m0 * m0), f);
+            D[1][e] = scl(scl(t1, (T)2 * m1) - scl(q, m1 * m1), f);
+            D[2][e] = scl(scl(t2, (T)2 * m2) - scl(q, m2 * m2), f);
+            D[3][e] = scl(scl(t1, m2) + scl(t2, m1) - scl(q, m1 * m2), fs);
+            D[4][e] = scl(scl(t0, m2) + scl(t2, m0) - scl(q, m0 * m2), fs);
+            D[5][e] = scl(scl(t0, m1) + scl(t1, m0) - scl(q, m0 * m1), fs);
+          } else {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) D[c][e] = mk<T>(0, 0);
+          }
+        }
+      }
+    }
+  }
+
+  // ---- inverse along axis 0
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+        DFT<NB, 1, T>::run(&D[c][j * NB]);
+        // D[c][j*NB + u] now holds Z_a[u], u = stage-A column index
+        if (a > 0) {
+#pragma unroll
+          for (int u = 1; u < NB; ++u) D[c][j * NB + u] = cmulc(D[c][j * NB + u], tw[(u * a) % N]);
+        }
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) lds[a * RS + u * W + w] = D[c][j * NB + u];
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int a = 0; a < NA; ++a) D[c][a] = lds[a * RS + t * W + w];
+    DFT<NA, 1, T>::run(D[c]);
+    if (ok) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) base[c * pstride + (long long)(t + NB * i) * g.n1] = D[c][i];
+    }
+  }
+}
+
+// ============================================================================ P5
+// grid (ceil(N1/W), N0, ncases), block W*NB threads, dyn. LDS W*max(NA*(NB+1), N+1) complex
+// partials[(cs*N0 + n0)*gridDim.x + blockIdx.x] = sum over the block of <y, dotv> (if dotv)
+template <typename T, int NA, int NB>
+__global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spec, T* __restrict__ y, const T* __restrict__ dotv,
+                            double* __restrict__ partials, const cx<T>* __restrict__ tw, GridDims g, int W,
+                            const MinresState* __restrict__ st) {
+  constexpr int N = NA * NB;
+  constexpr int TT = NB;
+  constexpr int CB = (NA + TT - 1) / TT;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  __shared__ double red[16];
+  const int cs = blockIdx.z;
+  if (st && st[cs].finish) return;
+  const int n0 = blockIdx.y;
+  const int n1_0 = blockIdx.x * W;
+  const int tid = threadIdx.x;
+  const int t = tid % TT, w = tid / TT;
+  const int n1 = n1_0 + w;
+  const bool row_ok = n1 < g.n1;
+  const int ws = tid % W, m = tid / W, M = blockDim.x / W;
+  const int n1s = n1_0 + ws;
+  const long long row = ((long long)n0 * g.n1 + n1) * N;
+  T* yc = y + (long long)cs * 6 * g.nvox;
+  const T* dc = dotv ? dotv + (long long)cs * 6 * g.nvox : nullptr;
+  double acc = 0.0;
+  // all six spectrum components this thread gathers, loaded up front
+  constexpr int LK = (N / 2 + 1 + TT - 1) / TT;
+  cx<T> sp[6][LK];
+#pragma unroll
+  for (int l = 0; l < LK; ++l) {
+    const int k = m + M * l;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      sp[c][l] = (n1s < g.n1 && k < g.k2) ? spec[spec_idx(g, cs, k, c, n0, n1s)] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int pr = 0; pr < 3; ++pr) {
+    // operand of the dot product for this pair, fetched early
+    T dv[CB][NB][2];
+    if (dc && row_ok) {
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        const int a = t + TT * j;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const long long o = row + a + NA * b;
+          dv[j][b][0] = (a < NA) ? dc[(2 * pr) * g.nvox + o] : (T)0;
+          dv[j][b][1] = (a < NA) ? dc[(2 * pr + 1) * g.nvox + o] : (T)0;
+        }
+      }
+    }
+    lds_barrier();
+    if (n1s < g.n1) {
+#pragma unroll
+      for (int l = 0; l < LK; ++l) {
+        const int k = m + M * l;
+        if (k < g.k2) {
+          const cx<T> A = sp[2 * pr][l];
+          const cx<T> B = sp[2 * pr + 1][l];
+          if (k == 0 || 2 * k == N) {
+            lds[ws * (N + 1) + k] = mk<T>(A.re, B.re);
+          } else {
+            lds[ws * (N + 1) + k] = mk<T>(A.re - B.im, A.im + B.re);
+            lds[ws * (N + 1) + N - k] = mk<T>(A.re + B.im, B.re - A.im);
+          }
+        }
+      }
+    }
+    lds_barrier();
+    cx<T> z[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) z[i] = lds[w * (N + 1) + t + NB * i];
+    DFT<NA, 1, T>::run(z);
+#pragma unroll
+    for (int a = 1; a < NA; ++a) z[a] = cmulc(z[a], tw[(t * a) % N]);
+    lds_barrier();
+#pragma unroll
+    for (int a = 0; a < NA; ++a) lds[(w * NA + a) * (NB + 1) + t] = z[a];
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+        cx<T> yb[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) yb[u] = lds[(w * NA + a) * (NB + 1) + u];
+        DFT<NB, 1, T>::run(yb);
+        if (row_ok) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const long long o = row + a + NA * b;
+            yc[(2 * pr) * g.nvox + o] = yb[b].re;
+            yc[(2 * pr + 1) * g.nvox + o] = yb[b].im;
+            if (dc) acc += (double)yb[b].re * (double)dv[j][b][0] + (double)yb[b].im * (double)dv[j][b][1];
+          }
+        }
+      }
+    }
+  }
+  if (partials) {
+    const double s = block_sum(acc, red);
+    if (tid == 0) partials[((long long)cs * g.n0 + n0) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+}  // namespace rve

@@ -1,0 +1,46 @@
+// Table of the compiled FFT pass kernels, one entry per supported axis length N = NA * NB.
+#pragma once
+#include "rve_kernels.h"
+
+namespace rve {
+
+template <typename T>
+using P1Fn = void (*)(const T*, const double*, int, const float*, Material<T>, cx<T>*, const cx<T>*, GridDims, int,
+                      const MinresState*);
+template <typename T>
+using P2Fn = void (*)(cx<T>*, const cx<T>*, GridDims, int, long long, const MinresState*);
+template <typename T>
+using P3Fn = void (*)(cx<T>*, const cx<T>*, FreqTables<T>, GridDims, int, T, int, const MinresState*);
+template <typename T>
+using P5Fn = void (*)(const cx<T>*, T*, const T*, double*, const cx<T>*, GridDims, int, const MinresState*);
+
+template <typename T>
+struct LenKernels {
+  P1Fn<T> p1;
+  P2Fn<T> p2f, p2i;
+  P3Fn<T> p3;
+  P5Fn<T> p5;
+};
+
+struct LenEntry {
+  int n, na, nb;
+  LenKernels<float> f;
+  LenKernels<double> d;
+  template <typename T>
+  const LenKernels<T>& k() const;
+};
+template <>
+inline const LenKernels<float>& LenEntry::k<float>() const { return f; }
+template <>
+inline const LenKernels<double>& LenEntry::k<double>() const { return d; }
+
+void register_len(const LenEntry& e);
+const LenEntry* find_len(int n);
+
+}  // namespace rve
+
+#define RVE_LEN_KERNELS(T_, NA_, NB_)                                                                  \
+  {&rve::k_fwd_axis2<T_, NA_, NB_>, &rve::k_axis1<T_, NA_, NB_, -1>, &rve::k_axis1<T_, NA_, NB_, 1>, \
+   &rve::k_axis0_project<T_, NA_, NB_>, &rve::k_inv_axis2<T_, NA_, NB_>}
+#define RVE_LEN_ENTRY(N_, NA_, NB_) \
+  rve::LenEntry { N_, NA_, NB_, RVE_LEN_KERNELS(float, NA_, NB_), RVE_LEN_KERNELS(double, NA_, NB_) }

@@ -1,0 +1,1178 @@
+// Host driver and Krylov kernels of the gfx950 Galerkin-FFT homogenization solver (C ABI in rve.h).
+//
+// One MINRES iteration is ten launches, all on one stream, no host involvement:
+//   P1..P5 (operator pass kernels, rve_kernels.h) -> S1 Lanczos alpha -> U1 Lanczos vector update
+//   -> S2 Givens QR step + convergence test -> U2 search direction + solution update.
+// Vectors carry a deferred normalisation: the Lanczos vector v_k is stored unscaled (u_k) and its
+// 1/beta_k is applied inside the consumers (P1 stiffness, U1, U2).
+// FP32_MIXED: fields and transforms in FP32, Krylov scalars and all inner products in FP64; the
+// outer loop recomputes the true residual with FP64 operator kernels and refines (x64 += delta).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/rve.h"
+#include "rve_registry.h"
+
+namespace rve {
+
+// ============================================================================ registry
+static std::vector<LenEntry>& registry() {
+  static std::vector<LenEntry> r;
+  return r;
+}
+void register_len(const LenEntry& e) { registry().push_back(e); }
+const LenEntry* find_len(int n) {
+  for (const auto& e : registry())
+    if (e.n == n) return &e;
+  return nullptr;
+}
+void register_group_a();
+void register_group_b();
+void register_group_c();
+static void ensure_registry() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    register_group_a();
+    register_group_b();
+    register_group_c();
+  });
+}
+
+// ============================================================================ per-kernel timing
+// Optional HIP-event timing of every launch inside the MINRES iteration loop (on the solve stream).
+// Events come from a pool created on first enable; pairs are read back at the host's chunk syncs.
+namespace prof {
+enum Kind { P1 = 0, P2, P3, P4, P5, S1, U1, S2, U2, NKIND };
+static const char* kNames[NKIND] = {"P1_stiffness_fft_axis2", "P2_fft_axis1", "P3_fft_axis0_projection",
+                                    "P4_ifft_axis1", "P5_ifft_axis2_dot", "S1_lanczos_alpha",
+                                    "U1_lanczos_update", "S2_givens", "U2_direction_update"};
+static bool on = false;
+static std::vector<hipEvent_t> pool;
+static std::vector<std::pair<int, int>> pending;
+static size_t next = 0;
+static double ms[NKIND];
+static long long cnt[NKIND];
+static long long dropped = 0;
+static std::mutex mu;
+static inline void begin(int kind, hipStream_t s) {
+  if (!on) return;
+  if (next + 2 > pool.size()) {
+    dropped++;
+    return;
+  }
+  hipEventRecord(pool[next], s);
+  pending.push_back({kind, (int)next});
+  next += 2;
+}
+static inline void end(hipStream_t s) {
+  if (!on || pending.empty() || (size_t)pending.back().second + 1 != next - 1) return;
+  hipEventRecord(pool[pending.back().second + 1], s);
+}
+static void flush() {
+  if (!on) return;
+  for (auto& pe : pending) {
+    float t = 0.f;
+    if (hipEventSynchronize(pool[pe.second + 1]) == hipSuccess &&
+        hipEventElapsedTime(&t, pool[pe.second], pool[pe.second + 1]) == hipSuccess) {
+      ms[pe.first] += t;
+      cnt[pe.first] += 1;
+    }
+  }
+  pending.clear();
+  next = 0;
+}
+}  // namespace prof
+
+// ============================================================================ small kernels
+constexpr int kRedBlocks = 2048;  // blocks per case for streaming vector kernels (and their partials)
+constexpr int kThreads = 256;
+
+// Frequency and twiddle tables per axis:
+//   tw[m] = exp(-2 pi i m / N)                                 (transform twiddles)
+//   rotated scheme:    s[m] = sin(q/2)/h, c[m] = cos(q/2)       (eq. freqrot, real direction)
+//   continuous scheme: s[m] = q/h,        c[m] = 1               (eq. freq)
+//   q = 2 pi k/N, k = m for m <= (N-1)/2 else m - N; at a Nyquist index c = 0 exactly, and with
+//   the zero-all Nyquist reading s = 0 too, so the projection vanishes there.
+template <typename T>
+__global__ void k_tables(cx<T>* tw, T* s, T* c, int N, double h, int scheme, int nyq_zero_all) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  double sn, cs;
+  sincospi(-2.0 * (double)m / (double)N, &sn, &cs);
+  tw[m] = mk<T>((T)cs, (T)sn);
+  const int k = (m <= (N - 1) / 2) ? m : m - N;
+  const bool nyq = (N % 2 == 0) && (2 * m == N);
+  double sh, ch;
+  sincospi((double)k / (double)N, &sh, &ch);  // half angle q/2 = pi k / N
+  double sv, cv;
+  if (scheme == RVE_SCHEME_CONTINUOUS) {
+    sv = 2.0 * kPi * (double)k / (double)N / h;
+    cv = 1.0;
+  } else {
+    sv = sh / h;
+    cv = ch;
+  }
+  if (nyq) {
+    cv = 0.0;
+    // the continuous scheme always zeroes Nyquist frequencies (otherwise the projection would not
+    // be even in k and the real-to-complex symmetry of the spectrum would break)
+    if (nyq_zero_all || scheme == RVE_SCHEME_CONTINUOUS) sv = 0.0;
+  }
+  s[m] = (T)sv;
+  c[m] = (T)cv;
+}
+
+template <typename T>
+__global__ void k_fill_const(T* x, const double* E /* [nc][6] */, long long nvox) {
+  const int cs = blockIdx.y;
+  T* xc = x + (long long)cs * 6 * nvox;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < 6 * nvox; i += (long long)gridDim.x * blockDim.x)
+    xc[i] = (T)E[cs * 6 + i / nvox];
+}
+
+template <typename T>
+__global__ void k_zero(T* x, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] = (T)0;
+}
+
+// out = alpha * a + beta * b (per case), partial sums of out^2
+template <typename Ta, typename To>
+__global__ void k_lincomb(To* out, const Ta* a, double alpha, const double* b, double beta, long long n6,
+                          double* partials) {
+  __shared__ double red[16];
+  const int cs = blockIdx.y;
+  const long long off = (long long)cs * n6;
+  double acc = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n6; i += (long long)gridDim.x * blockDim.x) {
+    double v = alpha * (double)a[off + i] + (b ? beta * b[off + i] : 0.0);
+    To o = (To)v;
+    out[off + i] = o;
+    acc += (double)o * (double)o;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0 && partials) partials[(long long)cs * gridDim.x + blockIdx.x] = s;
+}
+
+// x64 += (double) d  (per case, only where mask[cs] != 0)
+template <typename Td>
+__global__ void k_accum(double* x64, const Td* d, long long n6, const int* active) {
+  const int cs = blockIdx.y;
+  if (active && !active[cs]) return;
+  const long long off = (long long)cs * n6;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n6; i += (long long)gridDim.x * blockDim.x)
+    x64[off + i] += (double)d[off + i];
+}
+
+// deterministic per-case sum of partials[cs][0..np) -> out[cs * ostride]
+__global__ void k_sum_partials(const double* partials, int np, double* out, int ostride, int take_sqrt) {
+  __shared__ double red[16];
+  const int cs = blockIdx.x;
+  double acc = 0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[(long long)cs * np + i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) out[(long long)cs * ostride] = take_sqrt ? sqrt(s) : s;
+}
+
+// ---------------------------------------------------------------------------- MINRES scalars
+// Per-case bookkeeping of the whole solve.
+struct CaseInfo {
+  double bnorm;       // ||b||
+  double rnorm;       // ||b - A x64|| (last true residual)
+  int active;         // this case still needs an inner sweep
+  int iters;          // MINRES iterations summed over sweeps
+  int status;         // worst inner status
+  int pad;
+};
+
+// Start an inner MINRES on A d = r with u_1 = r (partials hold ||u_1||^2).
+__global__ void k_minres_init(MinresState* st, const double* partials, int np, CaseInfo* ci, double tol,
+                              double safety, double inner_floor, int max_iter) {
+  __shared__ double red[16];
+  const int cs = blockIdx.x;
+  double acc = 0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[(long long)cs * np + i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    MinresState& S = st[cs];
+    const double beta = sqrt(s);
+    S.beta = beta;
+    S.ib = beta > 0 ? 1.0 / beta : 0.0;
+    S.ib_prev = 0.0;
+    S.alpha = 0.0;
+    S.c1 = S.c2 = 1.0;
+    S.s1 = S.s2 = 0.0;
+    S.phibar = beta;
+    S.tol_abs = fmax(safety * tol * ci[cs].bnorm, inner_floor * beta);
+    S.cu_v = S.cu_vp = S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = 0.0;
+    S.iter = 0;
+    S.max_iter = max_iter - ci[cs].iters;
+    S.done = 0;
+    S.status = 0;
+    S.finish = (!ci[cs].active || beta <= S.tol_abs || S.max_iter <= 0) ? 1 : 0;
+  }
+}
+
+// S1: alpha_k = <A v_k, v_k> = ib_k * <p, u_k>; Lanczos coefficients for U1.
+__global__ void k_minres_alpha(MinresState* st, const double* partials, int np) {
+  __shared__ double red[16];
+  const int cs = blockIdx.x;
+  MinresState& S = st[cs];
+  if (S.done) return;
+  if (S.finish) {
+    __syncthreads();
+    if (threadIdx.x == 0) S.done = 1;
+    return;
+  }
+  double acc = 0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[(long long)cs * np + i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    const double alpha = S.ib * s;
+    S.alpha = alpha;
+    S.cu_v = alpha * S.ib;
+    S.cu_vp = S.beta * S.ib_prev;
+  }
+}
+
+// 16-byte vector access for the streaming vector kernels (falls back to scalars when a case's
+// field length is not a multiple of the vector width).
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+};
+
+// U1: p <- p - cu_v u_k - cu_vp u_{k-1} (= beta_{k+1} v_{k+1}), partial sums of p^2.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void k_lanczos(T* p, const T* uk, const T* ukm1, const MinresState* st,
+                                                 long long n6, double* partials) {
+  __shared__ double red[16];
+  const int cs = blockIdx.y;
+  const MinresState& S = st[cs];
+  if (S.done) return;
+  const T a = (T)S.cu_v, b = (T)S.cu_vp;
+  const long long off = (long long)cs * n6;
+  double acc = 0;
+  constexpr int V = VEC ? Vec16<T>::n : 1;
+  using VT = typename Vec16<T>::type;
+  const long long nv = n6 / V;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
+    if constexpr (VEC) {
+      VT pv = reinterpret_cast<const VT*>(p + off)[i];
+      const VT uv = reinterpret_cast<const VT*>(uk + off)[i];
+      const VT wv = reinterpret_cast<const VT*>(ukm1 + off)[i];
+      T* pe = reinterpret_cast<T*>(&pv);
+      const T* ue = reinterpret_cast<const T*>(&uv);
+      const T* we = reinterpret_cast<const T*>(&wv);
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        pe[e] = pe[e] - a * ue[e] - b * we[e];
+        acc += (double)pe[e] * (double)pe[e];
+      }
+      reinterpret_cast<VT*>(p + off)[i] = pv;
+    } else {
+      const T v = p[off + i] - a * uk[off + i] - b * ukm1[off + i];
+      p[off + i] = v;
+      acc += (double)v * (double)v;
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[(long long)cs * gridDim.x + blockIdx.x] = s;
+}
+
+// S2: beta_{k+1}; QR of the extended tridiagonal matrix by Givens rotations; residual recurrence.
+__global__ void k_minres_givens(MinresState* st, const double* partials, int np) {
+  __shared__ double red[16];
+  const int cs = blockIdx.x;
+  MinresState& S = st[cs];
+  if (S.done) return;
+  double acc = 0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[(long long)cs * np + i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x != 0) return;
+  const double beta_next = sqrt(s);
+  const double alpha = S.alpha, beta = S.beta;
+  const double eps = S.s2 * beta, dtil = S.c2 * beta;
+  const double delta = S.c1 * dtil + S.s1 * alpha;
+  const double gtil = -S.s1 * dtil + S.c1 * alpha;
+  const double gamma = hypot(gtil, beta_next);
+  S.iter += 1;
+  if (!(isfinite(alpha) && isfinite(beta_next) && isfinite(gamma))) {
+    S.status = RVE_ENONFINITE;
+    S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = 0.0;
+    S.finish = 1;
+    return;
+  }
+  if (gamma == 0.0) {
+    S.status = RVE_BREAKDOWN;
+    S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = 0.0;
+    S.finish = 1;
+    return;
+  }
+  const double c = gtil / gamma, sn = beta_next / gamma;
+  const double tau = c * S.phibar;
+  S.phibar = -sn * S.phibar;
+  S.cd_u = S.ib / gamma;
+  S.cd_d1 = -delta / gamma;
+  S.cd_d2 = -eps / gamma;
+  S.cx = tau;
+  S.c2 = S.c1;
+  S.s2 = S.s1;
+  S.c1 = c;
+  S.s1 = sn;
+  S.ib_prev = S.ib;
+  S.ib = beta_next > 0 ? 1.0 / beta_next : 0.0;
+  S.beta = beta_next;
+  const bool conv = fabs(S.phibar) <= S.tol_abs || beta_next == 0.0;
+  if (conv) {
+    S.finish = 1;
+  } else if (S.iter >= S.max_iter) {
+    S.status = RVE_NOT_CONVERGED;
+    S.finish = 1;
+  }
+}
+
+// U2: d_k = cd_u u_k + cd_d1 d_{k-1} + cd_d2 d_{k-2} (written over d_{k-2}); x += cx d_k.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* uk, T* x, const MinresState* st,
+                                                   long long n6) {
+  const int cs = blockIdx.y;
+  const MinresState& S = st[cs];
+  if (S.done) return;
+  const T a = (T)S.cd_u, b = (T)S.cd_d1, c = (T)S.cd_d2, xc = (T)S.cx;
+  const long long off = (long long)cs * n6;
+  constexpr int V = VEC ? Vec16<T>::n : 1;
+  using VT = typename Vec16<T>::type;
+  const long long nv = n6 / V;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
+    if constexpr (VEC) {
+      VT dv = reinterpret_cast<const VT*>(d2 + off)[i];
+      VT xv = reinterpret_cast<const VT*>(x + off)[i];
+      const VT uv = reinterpret_cast<const VT*>(uk + off)[i];
+      const VT d1v = reinterpret_cast<const VT*>(d1 + off)[i];
+      T* de = reinterpret_cast<T*>(&dv);
+      T* xe = reinterpret_cast<T*>(&xv);
+      const T* ue = reinterpret_cast<const T*>(&uv);
+      const T* d1e = reinterpret_cast<const T*>(&d1v);
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const T d = a * ue[e] + b * d1e[e] + c * de[e];
+        de[e] = d;
+        xe[e] += xc * d;
+      }
+      reinterpret_cast<VT*>(d2 + off)[i] = dv;
+      reinterpret_cast<VT*>(x + off)[i] = xv;
+    } else {
+      const T d = a * uk[off + i] + b * d1[off + i] + c * d2[off + i];
+      d2[off + i] = d;
+      x[off + i] += xc * d;
+    }
+  }
+}
+
+// Inner sweep bookkeeping: add iterations, record status.
+__global__ void k_sweep_done(const MinresState* st, CaseInfo* ci, int nc) {
+  const int cs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cs >= nc || !ci[cs].active) return;
+  ci[cs].iters += st[cs].iter;
+  if (st[cs].status != 0 && st[cs].status != RVE_NOT_CONVERGED) ci[cs].status = st[cs].status;
+  if (st[cs].status == RVE_NOT_CONVERGED) ci[cs].status = RVE_NOT_CONVERGED;
+}
+
+// After a true-residual evaluation: rnorm from the summed partial; decide whether another sweep runs.
+__global__ void k_residual_update(CaseInfo* ci, const double* sums, int nc, double tol, int max_iter) {
+  const int cs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cs >= nc) return;
+  ci[cs].rnorm = sqrt(sums[cs]);
+  const bool conv = ci[cs].bnorm == 0.0 || ci[cs].rnorm <= tol * ci[cs].bnorm;
+  const bool bad = ci[cs].status == RVE_ENONFINITE || ci[cs].status == RVE_BREAKDOWN;
+  ci[cs].active = (!conv && !bad && ci[cs].iters < max_iter) ? 1 : 0;
+}
+
+// Post-processing: sigma = C(x) (Ebar + eps) in FP64, write strain/stress in the output type,
+// per-block partial sums of each stress component.
+template <typename To>
+__global__ void k_post(const double* x64, const float* phi, Material<double> mat, const double* E, To* strain_out,
+                       To* stress_out, long long nvox, double* partials /* [nc][6][blocks] */) {
+  __shared__ double red[16];
+  const int cs = blockIdx.y;
+  const long long off = (long long)cs * 6 * nvox;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (long long)gridDim.x * blockDim.x) {
+    double e[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double f = x64[off + c * nvox + v];
+      if (strain_out) strain_out[off + c * nvox + v] = (To)f;
+      e[c] = E[cs * 6 + c] + f;
+    }
+    const double ph = phi[v];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      double s = 0, s0 = 0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        s += mat.Cd[a * 6 + b] * e[b];
+        s0 += mat.C0[a * 6 + b] * e[b];
+      }
+      const double sig = ph * s + s0;
+      acc[a] += sig;
+      if (stress_out) stress_out[off + a * nvox + v] = (To)sig;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    const double s = block_sum(acc[a], red);
+    if (threadIdx.x == 0) partials[((long long)cs * 6 + a) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// phi validity: counts of non-finite and out-of-range entries
+__global__ void k_check_phi(const float* phi, long long n, int* bad) {
+  int nb = 0, nr = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float v = phi[i];
+    if (!isfinite(v)) nb++;
+    else if (v < 0.0f || v > 1.0f) nr++;
+  }
+  if (nb) atomicAdd(&bad[0], nb);
+  if (nr) atomicAdd(&bad[1], nr);
+}
+
+// ============================================================================ plan + workspace
+static long long align_up(long long v, long long a) { return (v + a - 1) / a * a; }
+
+struct Plan {
+  int n[3];
+  GridDims g;
+  const LenEntry* ax[3];
+  int W1, W3, R2;  // P1/P5 row tile, P3 pencil tile, P2/P4 rows per block
+};
+
+static int pick_tile(int threads_per_row, int len) {
+  int W = std::max(1, std::min(64, 256 / threads_per_row));
+  while (W > 1 && W / 2 >= len) W /= 2;  // do not tile far beyond the axis length
+  return W;
+}
+
+// Largest tile not above the plan's choice whose dynamic LDS stays within 64 KiB.
+constexpr long long kLdsCap = 64 * 1024;
+static int tile_p1(const Plan& pl, int elem) {
+  const int na = pl.ax[2]->na, nb = pl.ax[2]->nb;
+  int W = pl.W1;
+  while (W > 1 && 2LL * elem * W * std::max(na * (nb + 1), pl.g.n2 + 1) > kLdsCap) W /= 2;
+  return W;
+}
+static int tile_p3(const Plan& pl, int elem) {
+  const int na = pl.ax[0]->na, nb = pl.ax[0]->nb;
+  int W = pl.W3;
+  while (W > 1 && 2LL * elem * na * (nb * W + 1) > kLdsCap) W /= 2;
+  return W;
+}
+static int rows_p2(const Plan& pl, int elem) {
+  const int na = pl.ax[1]->na, nb = pl.ax[1]->nb;
+  int R = pl.R2;
+  while (R > 1 && 2LL * elem * R * na * (nb + 1) > kLdsCap) R /= 2;
+  return R;
+}
+static int partials_p5(const Plan& pl, int elem) {
+  const int W = tile_p1(pl, elem);
+  return pl.g.n0 * ((pl.g.n1 + W - 1) / W);
+}
+
+static bool make_plan(const rve_grid* grid, Plan* pl) {
+  ensure_registry();
+  for (int p = 0; p < 3; ++p) {
+    pl->n[p] = grid->n[p];
+    pl->ax[p] = find_len(grid->n[p]);
+    if (!pl->ax[p]) return false;
+  }
+  GridDims& g = pl->g;
+  g.n0 = pl->n[0];
+  g.n1 = pl->n[1];
+  g.n2 = pl->n[2];
+  g.k2 = g.n2 / 2 + 1;
+  g.nvox = (long long)g.n0 * g.n1 * g.n2;
+  g.spec_case = 6LL * g.k2 * g.n0 * g.n1;
+  pl->W1 = pick_tile(pl->ax[2]->nb, g.n1);
+  pl->W3 = pick_tile(pl->ax[0]->nb, g.n1);
+  pl->R2 = std::max(1, std::min(64, 256 / pl->ax[1]->nb));
+  return true;
+}
+
+template <typename T>
+struct Tables {
+  cx<T>* tw[3];
+  T* s[3];
+  T* c[3];
+};
+
+// Workspace carve-out.  Sizes depend only on (grid, n_cases, precision).
+struct Layout {
+  long long off_state, off_info, off_part, off_sums, off_tab32, off_tab64, off_u32[3], off_d32[2], off_x32,
+      off_spec32, off_x64, off_b64, off_r64, off_spec64, off_u64[3], off_d64[2], off_flag, total;
+  int np_p5, np_vec, np_post;
+};
+
+static long long tab_bytes(const Plan& pl, int elem) {
+  long long b = 0;
+  for (int p = 0; p < 3; ++p) b += align_up((long long)pl.n[p] * (2 * elem) + 2LL * pl.n[p] * elem + 64, 256);
+  return b;
+}
+
+static Layout make_layout(const Plan& pl, int nc, int precision, bool solve) {
+  Layout L;
+  memset(&L, 0, sizeof(L));
+  const GridDims& g = pl.g;
+  const long long n6 = 6 * g.nvox * nc;
+  L.np_p5 = std::max(partials_p5(pl, 4), partials_p5(pl, 8));
+  L.np_vec = kRedBlocks;
+  L.np_post = 6 * kRedBlocks;
+  const int np_max = std::max(std::max(L.np_p5, L.np_vec), L.np_post);
+  long long o = 0;
+  auto take = [&](long long bytes) {
+    long long r = o;
+    o = align_up(o + bytes, 256);
+    return r;
+  };
+  L.off_state = take(sizeof(MinresState) * nc);
+  L.off_info = take(sizeof(CaseInfo) * nc);
+  L.off_part = take(sizeof(double) * (long long)np_max * nc);
+  L.off_sums = take(sizeof(double) * 8 * nc);
+  L.off_flag = take(64);
+  L.off_tab32 = take(tab_bytes(pl, 4));
+  L.off_tab64 = take(tab_bytes(pl, 8));
+  if (precision == RVE_FP32_MIXED) {
+    L.off_spec32 = take(8 * g.spec_case * nc);
+    if (solve) {
+      for (int i = 0; i < 3; ++i) L.off_u32[i] = take(4 * n6);
+      for (int i = 0; i < 2; ++i) L.off_d32[i] = take(4 * n6);
+      L.off_x32 = take(4 * n6);
+    }
+  } else if (solve) {
+    for (int i = 0; i < 3; ++i) L.off_u64[i] = take(8 * n6);
+    for (int i = 0; i < 2; ++i) L.off_d64[i] = take(8 * n6);
+  }
+  if (solve || precision == RVE_FP64) L.off_spec64 = take(16 * g.spec_case * nc);
+  if (solve) {
+    L.off_x64 = take(8 * n6);
+    L.off_b64 = take(8 * n6);
+    L.off_r64 = take(8 * n6);
+  }
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+static Tables<T> tables_at(const Plan& pl, char* base) {
+  Tables<T> t;
+  for (int p = 0; p < 3; ++p) {
+    t.tw[p] = reinterpret_cast<cx<T>*>(base);
+    t.s[p] = reinterpret_cast<T*>(base + sizeof(cx<T>) * pl.n[p]);
+    t.c[p] = t.s[p] + pl.n[p];
+    base += align_up((long long)pl.n[p] * (2 * sizeof(T)) + 2LL * pl.n[p] * sizeof(T) + 64, 256);
+  }
+  return t;
+}
+
+#define HIPCHK(x)                          \
+  do {                                     \
+    hipError_t e_ = (x);                   \
+    if (e_ != hipSuccess) return RVE_EDEVICE; \
+  } while (0)
+
+template <typename T>
+static rve_status build_tables(const Plan& pl, const rve_grid* grid, char* base, int scheme, int nyq, hipStream_t s) {
+  Tables<T> t = tables_at<T>(pl, base);
+  for (int p = 0; p < 3; ++p) {
+    const double h = grid->L[p] / pl.n[p];
+    hipLaunchKernelGGL(k_tables<T>, dim3((pl.n[p] + 255) / 256), dim3(256), 0, s, t.tw[p], t.s[p], t.c[p], pl.n[p], h,
+                       scheme, nyq);
+  }
+  HIPCHK(hipGetLastError());
+  return RVE_OK;
+}
+
+template <typename T>
+static Material<T> make_material(const double* Cvoid, const double* Csolid) {
+  Material<T> m;
+  bool any = false;
+  for (int i = 0; i < 36; ++i) {
+    m.C0[i] = (T)Cvoid[i];
+    m.Cd[i] = (T)(Csolid[i] - Cvoid[i]);
+    any = any || Cvoid[i] != 0.0;
+  }
+  m.has_c0 = any ? 1 : 0;
+  m.use_phi = 1;
+  return m;
+}
+
+// ---------------------------------------------------------------------------- operator apply
+// y = F^{-1}{ Ghat : F{ C(x) : xs * x } } for nc cases.  dotv/partials: optional <y, dotv> partials.
+template <typename T>
+static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, const float* phi,
+                     const Material<T>& mat, const Tables<T>& tb, cx<T>* spec, T* y, const T* dotv, double* partials,
+                     const MinresState* st, int identity, hipStream_t s) {
+  const GridDims& g = pl.g;
+  const LenKernels<T>& K0 = pl.ax[0]->k<T>();
+  const LenKernels<T>& K1 = pl.ax[1]->k<T>();
+  const LenKernels<T>& K2 = pl.ax[2]->k<T>();
+  const int na2 = pl.ax[2]->na, nb2 = pl.ax[2]->nb;
+  const int na1 = pl.ax[1]->na, nb1 = pl.ax[1]->nb;
+  const int na0 = pl.ax[0]->na, nb0 = pl.ax[0]->nb;
+  const int N2 = g.n2;
+  const int elem = (int)sizeof(T);
+  // P1
+  {
+    const int W = tile_p1(pl, elem);
+    const size_t lds = sizeof(cx<T>) * W * std::max(na2 * (nb2 + 1), N2 + 1);
+    dim3 grid((g.n1 + W - 1) / W, g.n0, nc);
+    prof::begin(prof::P1, s);
+    hipLaunchKernelGGL(K2.p1, grid, dim3(W * nb2), lds, s, x, xscale, (int)(sizeof(MinresState) / sizeof(double)),
+                       phi, mat, spec, tb.tw[2], g, W, st);
+    prof::end(s);
+  }
+  // P2
+  const long long rows = (long long)nc * g.k2 * 6 * g.n0;
+  {
+    const int R = rows_p2(pl, elem);
+    const size_t lds = sizeof(cx<T>) * R * na1 * (nb1 + 1);
+    prof::begin(prof::P2, s);
+    hipLaunchKernelGGL(K1.p2f, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, tb.tw[1], g, R, rows,
+                       st);
+    prof::end(s);
+  }
+  // P3
+  {
+    const int W = tile_p3(pl, elem);
+    const size_t lds = sizeof(cx<T>) * na0 * (nb0 * W + 1);
+    FreqTables<T> ft;
+    for (int p = 0; p < 3; ++p) {
+      ft.s[p] = tb.s[p];
+      ft.c[p] = tb.c[p];
+    }
+    dim3 grid((g.n1 + W - 1) / W, g.k2, nc);
+    prof::begin(prof::P3, s);
+    hipLaunchKernelGGL(K0.p3, grid, dim3(W * nb0), lds, s, spec, tb.tw[0], ft, g, W, (T)(1.0 / (double)g.nvox),
+                       identity, st);
+    prof::end(s);
+  }
+  // P4
+  {
+    const int R = rows_p2(pl, elem);
+    const size_t lds = sizeof(cx<T>) * R * na1 * (nb1 + 1);
+    prof::begin(prof::P4, s);
+    hipLaunchKernelGGL(K1.p2i, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, tb.tw[1], g, R, rows,
+                       st);
+    prof::end(s);
+  }
+  // P5
+  {
+    const int W = tile_p1(pl, elem);
+    const size_t lds = sizeof(cx<T>) * W * std::max(na2 * (nb2 + 1), N2 + 1);
+    dim3 grid((g.n1 + W - 1) / W, g.n0, nc);
+    prof::begin(prof::P5, s);
+    hipLaunchKernelGGL(K2.p5, grid, dim3(W * nb2), lds, s, spec, y, dotv, partials, tb.tw[2], g, W, st);
+    prof::end(s);
+  }
+}
+
+// ---------------------------------------------------------------------------- MINRES driver
+template <typename T>
+struct MinresBufs {
+  T* u[3];
+  T* d[2];
+  T* x;
+};
+
+static void vec_grid(int nc, dim3* grid, dim3* block) {
+  *grid = dim3(kRedBlocks, nc);
+  *block = dim3(kThreads);
+}
+
+// Runs MINRES iterations until every case has finished or the iteration budget is spent.
+// States must be initialised (k_minres_init).  Host polls the finish flags every `check` iterations.
+// Profiling covers only the MINRES iteration loop.
+struct ProfScope {
+  bool saved;
+  explicit ProfScope(bool enable) : saved(prof::on) { prof::on = prof::on && enable; }
+  ~ProfScope() { prof::on = saved; }
+};
+
+template <typename T>
+static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const float* phi, const Material<T>& mat,
+                              const Tables<T>& tb, cx<T>* spec, MinresState* st, double* part, int max_iter,
+                              int check, hipStream_t s) {
+  const int np_p5 = partials_p5(pl, (int)sizeof(T));
+  const long long n6 = 6 * pl.g.nvox;
+  dim3 vg, vb;
+  vec_grid(nc, &vg, &vb);
+  std::vector<MinresState> hs(nc);
+  ProfScope prof_scope(true);
+  // 16-byte access needs each case's field to start on a 16-byte boundary
+  const bool vec = (n6 * (long long)sizeof(T)) % 16 == 0;
+  int ia = 0, ib = 1, ic = 2, id1 = 0, id2 = 1;  // u_{k-1}, u_k, p ; d_{k-1}, d_{k-2}
+  int it = 0;
+  while (it < max_iter) {
+    const int chunk = std::min(check, max_iter - it);
+    for (int j = 0; j < chunk; ++j) {
+      apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], part, st, 0, s);
+      prof::begin(prof::S1, s);
+      hipLaunchKernelGGL(k_minres_alpha, dim3(nc), dim3(kThreads), 0, s, st, part, np_p5);
+      prof::end(s);
+      prof::begin(prof::U1, s);
+      if (vec)
+        hipLaunchKernelGGL((k_lanczos<T, true>), vg, vb, 0, s, B.u[ic], B.u[ib], B.u[ia], st, n6, part);
+      else
+        hipLaunchKernelGGL((k_lanczos<T, false>), vg, vb, 0, s, B.u[ic], B.u[ib], B.u[ia], st, n6, part);
+      prof::end(s);
+      prof::begin(prof::S2, s);
+      hipLaunchKernelGGL(k_minres_givens, dim3(nc), dim3(kThreads), 0, s, st, part, kRedBlocks);
+      prof::end(s);
+      prof::begin(prof::U2, s);
+      if (vec)
+        hipLaunchKernelGGL((k_direction<T, true>), vg, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
+      else
+        hipLaunchKernelGGL((k_direction<T, false>), vg, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
+      prof::end(s);
+      const int t0 = ia;
+      ia = ib;
+      ib = ic;
+      ic = t0;
+      std::swap(id1, id2);
+    }
+    it += chunk;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hs.data(), st, sizeof(MinresState) * nc, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    prof::flush();
+    bool all = true;
+    for (int c = 0; c < nc; ++c) all = all && hs[c].finish;
+    if (all) break;
+  }
+  return RVE_OK;
+}
+
+}  // namespace rve
+
+using namespace rve;
+
+// ============================================================================ C ABI
+extern "C" {
+
+void rve_default_options(rve_options* o) {
+  if (!o) return;
+  o->tol = 1e-6;
+  o->max_iter = 5000;
+  o->precision = RVE_FP32_MIXED;
+  o->max_refine = 4;
+  o->nyquist = RVE_NYQ_NATURAL;
+  o->scheme = RVE_SCHEME_ROTATED;
+  o->check_every = 24;
+  o->inner_floor = 1e-5;
+  o->inner_safety = 0.5;
+}
+
+int32_t rve_supported_length(int32_t n) {
+  ensure_registry();
+  return find_len(n) ? 1 : 0;
+}
+
+void rve_profile_enable(int32_t on_) {
+  std::lock_guard<std::mutex> lk(prof::mu);
+  if (on_ && prof::pool.empty()) {
+    prof::pool.resize(2048);
+    for (auto& e : prof::pool)
+      if (hipEventCreate(&e) != hipSuccess) {
+        prof::pool.clear();
+        return;
+      }
+  }
+  prof::on = on_ != 0 && !prof::pool.empty();
+}
+
+void rve_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(prof::mu);
+  for (int k = 0; k < prof::NKIND; ++k) {
+    prof::ms[k] = 0;
+    prof::cnt[k] = 0;
+  }
+  prof::dropped = 0;
+}
+
+int32_t rve_profile_read(double* total_ms, int64_t* launches, int32_t max_kinds) {
+  std::lock_guard<std::mutex> lk(prof::mu);
+  const int n = std::min<int>(max_kinds, prof::NKIND);
+  for (int k = 0; k < n; ++k) {
+    if (total_ms) total_ms[k] = prof::ms[k];
+    if (launches) launches[k] = prof::cnt[k];
+  }
+  return prof::NKIND;
+}
+
+const char* rve_profile_kind_name(int32_t k) { return (k >= 0 && k < prof::NKIND) ? prof::kNames[k] : ""; }
+
+const char* rve_status_string(rve_status s) {
+  switch (s) {
+    case RVE_OK: return "RVE_OK";
+    case RVE_NOT_CONVERGED: return "RVE_NOT_CONVERGED";
+    case RVE_BREAKDOWN: return "RVE_BREAKDOWN";
+    case RVE_EINVAL: return "RVE_EINVAL";
+    case RVE_EUNSUPPORTED_SIZE: return "RVE_EUNSUPPORTED_SIZE";
+    case RVE_ENONFINITE: return "RVE_ENONFINITE";
+    case RVE_ENOMEM: return "RVE_ENOMEM";
+    case RVE_EDEVICE: return "RVE_EDEVICE";
+  }
+  return "RVE_UNKNOWN";
+}
+
+static rve_status validate_grid(const rve_grid* grid) {
+  if (!grid) return RVE_EINVAL;
+  for (int p = 0; p < 3; ++p) {
+    if (grid->n[p] < 1 || !(std::isfinite(grid->L[p]) && grid->L[p] > 0)) return RVE_EINVAL;
+  }
+  for (int p = 0; p < 3; ++p)
+    if (!rve_supported_length(grid->n[p])) return RVE_EUNSUPPORTED_SIZE;
+  return RVE_OK;
+}
+
+static rve_status validate_stiffness(const double* C) {
+  if (!C) return RVE_EINVAL;
+  for (int ph = 0; ph < 2; ++ph) {
+    const double* M = C + 36 * ph;
+    double mx = 0;
+    for (int i = 0; i < 36; ++i) {
+      if (!std::isfinite(M[i])) return RVE_ENONFINITE;
+      mx = std::max(mx, std::fabs(M[i]));
+    }
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j)
+        if (std::fabs(M[i * 6 + j] - M[j * 6 + i]) > 1e-12 * mx) return RVE_EINVAL;
+  }
+  return RVE_OK;
+}
+
+static rve_status validate_options(const rve_options* o) {
+  if (!o) return RVE_EINVAL;
+  if (!(std::isfinite(o->tol) && o->tol > 0)) return RVE_EINVAL;
+  if (o->max_iter < 1 || o->max_refine < 1 || o->check_every < 1) return RVE_EINVAL;
+  if (o->precision != RVE_FP32_MIXED && o->precision != RVE_FP64) return RVE_EINVAL;
+  if (o->nyquist != RVE_NYQ_NATURAL && o->nyquist != RVE_NYQ_ZERO_ALL) return RVE_EINVAL;
+  if (o->scheme != RVE_SCHEME_ROTATED && o->scheme != RVE_SCHEME_CONTINUOUS) return RVE_EINVAL;
+  if (!(o->inner_floor > 0 && o->inner_floor < 1) || !(o->inner_safety > 0 && o->inner_safety <= 1))
+    return RVE_EINVAL;
+  return RVE_OK;
+}
+
+rve_status rve_validate(const rve_grid* grid, const double* phase_stiffness, const double* macro_strain,
+                        int32_t n_cases, const rve_options* opt) {
+  rve_status s = validate_grid(grid);
+  if (s != RVE_OK) return s;
+  if (n_cases < 1 || n_cases > 65535) return RVE_EINVAL;
+  s = validate_options(opt);
+  if (s != RVE_OK) return s;
+  s = validate_stiffness(phase_stiffness);
+  if (s != RVE_OK) return s;
+  if (!macro_strain) return RVE_EINVAL;
+  for (int i = 0; i < 6 * n_cases; ++i)
+    if (!std::isfinite(macro_strain[i])) return RVE_ENONFINITE;
+  return RVE_OK;
+}
+
+size_t rve_workspace_bytes(const rve_grid* grid, int32_t n_cases, const rve_options* opt) {
+  if (validate_grid(grid) != RVE_OK || n_cases < 1 || validate_options(opt) != RVE_OK) return 0;
+  Plan pl;
+  if (!make_plan(grid, &pl)) return 0;
+  return (size_t)make_layout(pl, n_cases, opt->precision, true).total;
+}
+
+size_t rve_apply_workspace_bytes(const rve_grid* grid, int32_t n_cases, int32_t precision) {
+  if (validate_grid(grid) != RVE_OK || n_cases < 1 || (precision != RVE_FP32_MIXED && precision != RVE_FP64)) return 0;
+  Plan pl;
+  if (!make_plan(grid, &pl)) return 0;
+  return (size_t)make_layout(pl, n_cases, precision, false).total;
+}
+
+rve_status rve_apply(const rve_grid* grid, const float* phi, const double* phase_stiffness, int32_t n_cases,
+                     int32_t precision, int32_t scheme, int32_t nyquist, int32_t mode, const void* x, void* y,
+                     void* workspace, size_t workspace_bytes, void* hip_stream) {
+  rve_status st = validate_grid(grid);
+  if (st != RVE_OK) return st;
+  if (n_cases < 1 || n_cases > 65535) return RVE_EINVAL;
+  if (precision != RVE_FP32_MIXED && precision != RVE_FP64) return RVE_EINVAL;
+  if (scheme != RVE_SCHEME_ROTATED && scheme != RVE_SCHEME_CONTINUOUS) return RVE_EINVAL;
+  if (nyquist != RVE_NYQ_NATURAL && nyquist != RVE_NYQ_ZERO_ALL) return RVE_EINVAL;
+  if (mode < 0 || mode > 2) return RVE_EINVAL;
+  if (!x || !y || !workspace) return RVE_EINVAL;
+  if (mode != RVE_APPLY_PROJECTION) {
+    if (!phi) return RVE_EINVAL;
+    st = validate_stiffness(phase_stiffness);
+    if (st != RVE_OK) return st;
+  }
+  Plan pl;
+  if (!make_plan(grid, &pl)) return RVE_EUNSUPPORTED_SIZE;
+  const Layout L = make_layout(pl, n_cases, precision, false);
+  if ((long long)workspace_bytes < L.total) return RVE_ENOMEM;
+  hipStream_t s = (hipStream_t)hip_stream;
+  char* ws = (char*)workspace;
+  double ident[72] = {0};
+  for (int i = 0; i < 6; ++i) ident[i * 7] = 1.0;  // void phase = identity, solid = identity
+  for (int i = 0; i < 6; ++i) ident[36 + i * 7] = 1.0;
+  const double* C = (mode == RVE_APPLY_PROJECTION) ? ident : phase_stiffness;
+  if (precision == RVE_FP32_MIXED) {
+    rve_status r = build_tables<float>(pl, grid, ws + L.off_tab32, scheme, nyquist, s);
+    if (r != RVE_OK) return r;
+    Tables<float> tb = tables_at<float>(pl, ws + L.off_tab32);
+    Material<float> mat = make_material<float>(C, C + 36);
+    if (mode == RVE_APPLY_PROJECTION) {
+      // C = identity independent of phi: C0 = I and phi is not read
+      for (int i = 0; i < 36; ++i) mat.Cd[i] = 0.0f;
+      mat.has_c0 = 1;
+      mat.use_phi = 0;
+    }
+    apply_op<float>(pl, n_cases, (const float*)x, nullptr, phi, mat, tb, (cx<float>*)(ws + L.off_spec32), (float*)y,
+                    nullptr, nullptr, nullptr, mode == RVE_APPLY_STIFFNESS_ROUNDTRIP, s);
+  } else {
+    rve_status r = build_tables<double>(pl, grid, ws + L.off_tab64, scheme, nyquist, s);
+    if (r != RVE_OK) return r;
+    Tables<double> tb = tables_at<double>(pl, ws + L.off_tab64);
+    Material<double> mat = make_material<double>(C, C + 36);
+    if (mode == RVE_APPLY_PROJECTION) {
+      for (int i = 0; i < 36; ++i) mat.Cd[i] = 0.0;
+      mat.has_c0 = 1;
+      mat.use_phi = 0;
+    }
+    apply_op<double>(pl, n_cases, (const double*)x, nullptr, phi, mat, tb, (cx<double>*)(ws + L.off_spec64),
+                     (double*)y, nullptr, nullptr, nullptr, mode == RVE_APPLY_STIFFNESS_ROUNDTRIP, s);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return RVE_OK;
+}
+
+rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase_stiffness,
+                     const double* macro_strain, int32_t n_cases, const rve_options* opt, const void* eps0,
+                     void* strain_out, void* stress_out, double* eff_stress, int32_t* iterations,
+                     double* rel_residual, void* workspace, size_t workspace_bytes, void* hip_stream) {
+  rve_status st = rve_validate(grid, phase_stiffness, macro_strain, n_cases, opt);
+  if (st != RVE_OK) return st;
+  if (!phi || !strain_out || !eff_stress || !iterations || !rel_residual || !workspace) return RVE_EINVAL;
+  Plan pl;
+  if (!make_plan(grid, &pl)) return RVE_EUNSUPPORTED_SIZE;
+  const int nc = n_cases;
+  const int prec = opt->precision;
+  const Layout L = make_layout(pl, nc, prec, true);
+  if ((long long)workspace_bytes < L.total) return RVE_ENOMEM;
+  hipStream_t s = (hipStream_t)hip_stream;
+  char* ws = (char*)workspace;
+  const GridDims& g = pl.g;
+  const long long n6 = 6 * g.nvox;
+
+  MinresState* dst = reinterpret_cast<MinresState*>(ws + L.off_state);
+  CaseInfo* dci = reinterpret_cast<CaseInfo*>(ws + L.off_info);
+  double* part = reinterpret_cast<double*>(ws + L.off_part);
+  double* sums = reinterpret_cast<double*>(ws + L.off_sums);
+  int* flag = reinterpret_cast<int*>(ws + L.off_flag);
+  double* x64 = reinterpret_cast<double*>(ws + L.off_x64);
+  double* b64 = reinterpret_cast<double*>(ws + L.off_b64);
+  double* r64 = reinterpret_cast<double*>(ws + L.off_r64);
+  cx<double>* spec64 = reinterpret_cast<cx<double>*>(ws + L.off_spec64);
+
+  // phi validity (device pre-pass)
+  HIPCHK(hipMemsetAsync(flag, 0, 64, s));
+  hipLaunchKernelGGL(k_check_phi, dim3(256), dim3(256), 0, s, phi, g.nvox, flag);
+  int hflag[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hflag[0]) return RVE_ENONFINITE;
+  if (hflag[1]) return RVE_EINVAL;
+
+  // tables, material, macro strains
+  rve_status r = build_tables<double>(pl, grid, ws + L.off_tab64, opt->scheme, opt->nyquist, s);
+  if (r != RVE_OK) return r;
+  Tables<double> tb64 = tables_at<double>(pl, ws + L.off_tab64);
+  Material<double> mat64 = make_material<double>(phase_stiffness, phase_stiffness + 36);
+  Tables<float> tb32;
+  Material<float> mat32 = make_material<float>(phase_stiffness, phase_stiffness + 36);
+  if (prec == RVE_FP32_MIXED) {
+    r = build_tables<float>(pl, grid, ws + L.off_tab32, opt->scheme, opt->nyquist, s);
+    if (r != RVE_OK) return r;
+    tb32 = tables_at<float>(pl, ws + L.off_tab32);
+  }
+  // macro strains live in the partials buffer's head while b is formed
+  double* Ed = part;
+  HIPCHK(hipMemcpyAsync(Ed, macro_strain, sizeof(double) * 6 * nc, hipMemcpyHostToDevice, s));
+  dim3 vg, vb;
+  vec_grid(nc, &vg, &vb);
+  // b = -A(Ebar)   (FP64 operator)
+  hipLaunchKernelGGL(k_fill_const<double>, vg, vb, 0, s, x64, Ed, g.nvox);
+  apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, 0, s);
+  std::vector<double> hE(macro_strain, macro_strain + 6 * nc);
+  // ||b||: b = -r64
+  hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, b64, r64, -1.0, (const double*)nullptr, 0.0, n6,
+                     part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums, 1, 1);
+  // CaseInfo init on host then upload
+  std::vector<CaseInfo> hci(nc);
+  std::vector<double> hb(nc);
+  HIPCHK(hipMemcpyAsync(hb.data(), sums, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int c = 0; c < nc; ++c) {
+    hci[c].bnorm = hb[c];
+    hci[c].rnorm = hb[c];
+    hci[c].iters = 0;
+    hci[c].status = 0;
+    hci[c].pad = 0;
+    hci[c].active = 1;
+  }
+  // A right-hand side at the rounding level of the transforms of a constant field counts as zero:
+  // the homogeneous case, answered exactly by eps = 0.
+  {
+    double scale = 0;
+    for (int c = 0; c < nc; ++c) {
+      double cn = 0;
+      for (int i = 0; i < 36; ++i) cn = std::max(cn, std::fabs(phase_stiffness[36 + i]));
+      double en = 0;
+      for (int i = 0; i < 6; ++i) en = std::max(en, std::fabs(hE[c * 6 + i]));
+      scale = cn * en * std::sqrt((double)n6);
+      if (hci[c].bnorm <= 1e-13 * scale) {
+        hci[c].bnorm = 0.0;
+        hci[c].active = 0;
+      }
+    }
+  }
+  HIPCHK(hipMemcpyAsync(dci, hci.data(), sizeof(CaseInfo) * nc, hipMemcpyHostToDevice, s));
+  // re-upload Ebar (part was overwritten by the norm partials)
+  double* Ed2 = sums;  // needs 6*nc doubles: sums holds 8*nc
+  HIPCHK(hipMemcpyAsync(Ed2, macro_strain, sizeof(double) * 6 * nc, hipMemcpyHostToDevice, s));
+
+  // start: x64 = 0 or projected warm start; r64 = b - A x64
+  if (eps0) {
+    // x64 = Ghat eps0 (projection, C = identity)
+    Material<double> id;
+    memset(&id, 0, sizeof(id));
+    for (int i = 0; i < 6; ++i) id.C0[i * 7] = 1.0;
+    id.has_c0 = 1;
+    id.use_phi = 0;
+    if (prec == RVE_FP32_MIXED) {
+      hipLaunchKernelGGL((k_lincomb<float, double>), vg, vb, 0, s, r64, (const float*)eps0, 1.0,
+                         (const double*)nullptr, 0.0, n6, part);
+    } else {
+      hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, (const double*)eps0, 1.0,
+                         (const double*)nullptr, 0.0, n6, part);
+    }
+    apply_op<double>(pl, nc, r64, nullptr, phi, id, tb64, spec64, x64, nullptr, nullptr, nullptr, 0, s);
+    apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, 0, s);
+    hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
+    hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
+                       opt->max_iter);
+  } else {
+    hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, x64, n6 * nc);
+    HIPCHK(hipMemcpyAsync(r64, b64, sizeof(double) * n6 * nc, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(hipGetLastError());
+
+  const int check = opt->check_every;
+  if (prec == RVE_FP32_MIXED) {
+    MinresBufs<float> B;
+    for (int i = 0; i < 3; ++i) B.u[i] = reinterpret_cast<float*>(ws + L.off_u32[i]);
+    for (int i = 0; i < 2; ++i) B.d[i] = reinterpret_cast<float*>(ws + L.off_d32[i]);
+    B.x = reinterpret_cast<float*>(ws + L.off_x32);
+    cx<float>* spec32 = reinterpret_cast<cx<float>*>(ws + L.off_spec32);
+    for (int sweep = 0; sweep < opt->max_refine; ++sweep) {
+      // any case active?
+      HIPCHK(hipMemcpyAsync(hci.data(), dci, sizeof(CaseInfo) * nc, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool any = false;
+      for (int c = 0; c < nc; ++c) any = any || hci[c].active;
+      if (!any) break;
+      // u_1 = fp32(r64), u_0 = d = x32 = 0
+      hipLaunchKernelGGL((k_lincomb<double, float>), vg, vb, 0, s, B.u[1], r64, 1.0, (const double*)nullptr, 0.0,
+                         n6, part);
+      hipLaunchKernelGGL(k_minres_init, dim3(nc), dim3(kThreads), 0, s, dst, part, kRedBlocks, dci, opt->tol,
+                         opt->inner_safety, opt->inner_floor, opt->max_iter);
+      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B.u[0], n6 * nc);
+      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B.d[0], n6 * nc);
+      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B.d[1], n6 * nc);
+      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B.x, n6 * nc);
+      // rotate buffers so that u_{k-1} = u[0], u_k = u[1], p = u[2]
+      r = minres_loop<float>(pl, nc, B, phi, mat32, tb32, spec32, dst, part, opt->max_iter, check, s);
+      if (r != RVE_OK) return r;
+      hipLaunchKernelGGL(k_sweep_done, dim3((nc + 63) / 64), dim3(64), 0, s, dst, dci, nc);
+      // x64 += x32 ; r64 = b - A x64
+      hipLaunchKernelGGL(k_accum<float>, vg, vb, 0, s, x64, B.x, n6, (const int*)nullptr);
+      apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, 0, s);
+      hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
+      hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
+      hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
+                         opt->max_iter);
+      HIPCHK(hipGetLastError());
+    }
+  } else {
+    MinresBufs<double> B;
+    for (int i = 0; i < 3; ++i) B.u[i] = reinterpret_cast<double*>(ws + L.off_u64[i]);
+    for (int i = 0; i < 2; ++i) B.d[i] = reinterpret_cast<double*>(ws + L.off_d64[i]);
+    B.x = x64;
+    // FP64: one MINRES on A x = b from the start x64 (r64 = b - A x64)
+    hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, B.u[1], r64, 1.0, (const double*)nullptr, 0.0, n6,
+                       part);
+    hipLaunchKernelGGL(k_minres_init, dim3(nc), dim3(kThreads), 0, s, dst, part, kRedBlocks, dci, opt->tol, 1.0,
+                       1e-300, opt->max_iter);
+    hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, B.u[0], n6 * nc);
+    hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, B.d[0], n6 * nc);
+    hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, B.d[1], n6 * nc);
+    r = minres_loop<double>(pl, nc, B, phi, mat64, tb64, spec64, dst, part, opt->max_iter, check, s);
+    if (r != RVE_OK) return r;
+    hipLaunchKernelGGL(k_sweep_done, dim3((nc + 63) / 64), dim3(64), 0, s, dst, dci, nc);
+    apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, 0, s);
+    hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
+    hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
+                       opt->max_iter);
+  }
+  HIPCHK(hipGetLastError());
+
+  // post-processing: strain/stress fields and <sigma>
+  HIPCHK(hipMemcpyAsync(Ed2, macro_strain, sizeof(double) * 6 * nc, hipMemcpyHostToDevice, s));
+  if (prec == RVE_FP32_MIXED) {
+    hipLaunchKernelGGL(k_post<float>, dim3(kRedBlocks, nc), dim3(kThreads), 0, s, x64, phi, mat64, Ed2,
+                       (float*)strain_out, (float*)stress_out, g.nvox, part);
+  } else {
+    hipLaunchKernelGGL(k_post<double>, dim3(kRedBlocks, nc), dim3(kThreads), 0, s, x64, phi, mat64, Ed2,
+                       (double*)strain_out, (double*)stress_out, g.nvox, part);
+  }
+  hipLaunchKernelGGL(k_sum_partials, dim3(6 * nc), dim3(kThreads), 0, s, part, kRedBlocks, r64, 1, 0);
+  std::vector<double> hs(6 * nc);
+  HIPCHK(hipMemcpyAsync(hs.data(), r64, sizeof(double) * 6 * nc, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hci.data(), dci, sizeof(CaseInfo) * nc, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  rve_status worst_err = RVE_OK, worst_warn = RVE_OK;
+  for (int c = 0; c < nc; ++c) {
+    for (int a = 0; a < 6; ++a) eff_stress[c * 6 + a] = hs[c * 6 + a] / (double)g.nvox;
+    iterations[c] = hci[c].iters;
+    rel_residual[c] = hci[c].bnorm > 0 ? hci[c].rnorm / hci[c].bnorm : 0.0;
+    if (hci[c].status == RVE_ENONFINITE || !std::isfinite(rel_residual[c])) worst_err = RVE_ENONFINITE;
+    else if (hci[c].status == RVE_BREAKDOWN) worst_warn = RVE_BREAKDOWN;
+    else if (hci[c].bnorm > 0 && !(rel_residual[c] <= opt->tol) && worst_warn == RVE_OK) worst_warn = RVE_NOT_CONVERGED;
+  }
+  rve_status worst = worst_err != RVE_OK ? worst_err : worst_warn;
+  return worst;
+}
+
+}  // extern "C"

@@ -1,7 +1,11 @@
 import os
 import sys
 
-import pytest
+# The CPU checker's OpenMP threads must not spin between parallel regions: the tests interleave it
+# with numpy's own BLAS threads, and spinning workers starve them.
+os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
+
+import pytest  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:

@@ -1,0 +1,293 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU checker.
+
+Tolerances: FP64 kernels agree with the checker to ~1e-12 relative; FP32 kernels to a few
+units of u32 * log2(N) (u32 = 6e-8), written below as 2e-5 relative to the field maximum.
+Solves: FP64 iterations within 1 of the checker and <sigma> within 1e-9; FP32-mixed C_eff within
+1e-5 relative (Frobenius) of the checker's FP64 C_eff.
+"""
+import numpy as np
+import pytest
+
+import lattice_inputs as li
+import oracle
+from tests import bruteforce as bf
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+C1 = li.isotropic_mandel(1.0, 0.3)
+C_SOFT = li.isotropic_mandel(0.05, 0.25)
+
+
+def _rve():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_00733_amd as rve
+    return rve
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# grids covering every compiled axis length on each axis, odd contiguous axes and ragged tiles
+GRIDS = [(2, 3, 4), (4, 5, 6), (6, 8, 5), (8, 12, 16), (16, 24, 12), (24, 16, 32), (12, 48, 24),
+         (32, 64, 48), (48, 32, 96), (96, 12, 64), (16, 128, 8), (128, 8, 16), (8, 16, 256), (256, 4, 8),
+         (4, 256, 2), (3, 2, 128)]
+
+
+@pytest.mark.parametrize("n", GRIDS)
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_stiffness_fft_roundtrip(n, dt):
+    """P1..P5 with the projection replaced by the identity: y = C(x) x exactly (up to rounding)."""
+    rve = _rve()
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    phi = li.random_phi(n, 1, 0.3)
+    x = li.random_field((2, 6) + n, 2)
+    y = rve.apply(_dev(x, tdt), _dev(phi), C1, C_void=C_SOFT, mode=rve.APPLY_STIFFNESS_ROUNDTRIP).cpu().numpy()
+    Cx = phi.astype(np.float64)[None, None] * np.einsum("ab,cb...->ca...", C1 - C_SOFT, x) + \
+        np.einsum("ab,cb...->ca...", C_SOFT, x)
+    tol = 1e-13 if dt == "f64" else 2e-6
+    assert _rel(y, Cx) < tol
+
+
+PROJ_GRIDS = [(4, 6, 8), (5, 3, 4), (6, 4, 5), (16, 16, 16), (12, 24, 32), (48, 32, 64), (96, 16, 12)]
+
+
+@pytest.mark.parametrize("n", PROJ_GRIDS)
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("nyq", [0, 1])
+def test_projection_vs_oracle(n, dt, nyq):
+    rve = _rve()
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    L = (1.0, 1.3, 0.7)
+    x = li.random_field((6,) + n, 3)
+    y = rve.apply(_dev(x[None], tdt), None, mode=rve.APPLY_PROJECTION, L=L, nyquist=nyq).cpu().numpy()[0]
+    ref = oracle.project(n, x, L=L, nyquist=nyq)
+    assert _rel(y, ref) < (1e-12 if dt == "f64" else 2e-5)
+
+
+@pytest.mark.parametrize("n", [(8, 12, 16), (16, 16, 16)])
+def test_continuous_scheme_projection_vs_oracle(n):
+    rve = _rve()
+    x = li.random_field((6,) + n, 4)
+    y = rve.apply(_dev(x[None], torch.float64), None, mode=rve.APPLY_PROJECTION, scheme=rve.CONTINUOUS,
+                  nyquist=rve.NYQ_ZERO_ALL).cpu().numpy()[0]
+    ref = oracle.project(n, x, scheme=oracle.CONTINUOUS, nyquist=oracle.NYQ_ZERO_ALL)
+    assert _rel(y, ref) < 1e-12
+
+
+OP_GRIDS = [(4, 6, 8), (5, 3, 4), (16, 24, 12), (32, 32, 32), (24, 48, 64), (64, 96, 32), (128, 128, 128)]
+
+
+@pytest.mark.parametrize("n", OP_GRIDS)
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_operator_vs_oracle(n, dt):
+    rve = _rve()
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    phi = li.random_phi(n, 5, 0.5)
+    x = li.random_field((6,) + n, 6)
+    Cv = C_SOFT if n[0] % 2 else None
+    y = rve.apply(_dev(x[None], tdt), _dev(phi), C1, C_void=Cv).cpu().numpy()[0]
+    ref = oracle.apply(n, phi, C1, x, C0=Cv)
+    assert _rel(y, ref) < (1e-12 if dt == "f64" else 2e-5)
+
+
+def test_batched_cases_match_single():
+    rve = _rve()
+    n = (16, 24, 32)
+    phi = _dev(li.random_phi(n, 7, 0.5))
+    x = li.random_field((3, 6) + n, 8)
+    yb = rve.apply(_dev(x), phi, C1).cpu().numpy()
+    for c in range(3):
+        ys = rve.apply(_dev(x[c:c + 1]), phi, C1).cpu().numpy()[0]
+        assert np.array_equal(yb[c], ys)
+
+
+def test_solve_fp64_matches_oracle_octet32():
+    """32^3 ideal octet, 10% density, uniaxial macro strain 1e-3, FP64, tol 1e-8."""
+    rve = _rve()
+    n = (32, 32, 32)
+    phi, _ = li.octet_phase_map(n, 0.10)
+    E = li.uniaxial_strain(1e-3)
+    ref = oracle.solve(n, phi, C1, E, tol=1e-8, maxit=2000)
+    out = rve.solve(_dev(phi), C1, E[None], precision=rve.FP64, tol=1e-8, max_iter=2000)
+    assert out["status"] == 0
+    assert abs(int(out["iterations"][0]) - ref["iterations"]) <= 1
+    assert out["rel_residual"][0] <= 1e-8
+    # both runs take the same Krylov steps; their FP64 rounding, amplified over ~200 Lanczos steps,
+    # leaves <sigma> differences near 1e-10 - two orders below what the 1e-8 tolerance allows
+    assert _rel(out["eff_stress"][0], ref["sigma_mean"]) < 1e-9
+    sig = out["stress"].cpu().numpy()[0]
+    assert _rel(sig, ref["sigma"]) < 5e-8
+    eps = out["strain"].cpu().numpy()[0]
+    solid = phi > 0
+    assert np.abs(eps[:, solid] - ref["eps"][:, solid]).max() < 1e-7 * np.abs(ref["eps"]).max()
+
+
+def _ceff_golden(n, rho):
+    import json
+    import os
+    p = os.path.join(os.path.dirname(__file__), "golden", f"ceff_octet_{n}.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p)).get(f"{rho:.4f}")
+    return None if d is None else np.array(d["C"])
+
+
+@pytest.mark.parametrize("n,rho", [(32, 0.05), (32, 0.10), (32, 0.20), (64, 0.05), (64, 0.10), (64, 0.20)])
+def test_fp32_mixed_effective_stiffness_vs_oracle(n, rho):
+    """Six unit Mandel load cases batched in one call, FP32 operator + FP64 refinement.  The
+    residual tolerance is 1e-8: on these compliant lattices a 1e-6 residual still leaves a few 1e-5
+    in C_eff, whatever the precision, so the 1e-5 C_eff target needs the tighter solve."""
+    rve = _rve()
+    ref = _ceff_golden(n, rho)
+    if ref is None:
+        pytest.skip(f"golden for {n}^3 rho={rho} not generated")
+    phi, _ = li.octet_phase_map(n, rho)
+    out = rve.solve(_dev(phi), C1, np.eye(6), tol=1e-8, want_stress=False)
+    assert out["status"] == 0, rve.status_string(out["status"])
+    assert np.all(out["rel_residual"] <= 1e-8)
+    Ce = out["eff_stress"].T
+    err = np.linalg.norm(Ce - ref) / np.linalg.norm(ref)
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("n,axis,prof", [((8, 4, 4), 0, [1, 1, 1, 1, .25, .25, .25, .25]),
+                                         ((5, 6, 3), 1, [1, 0.5, 0, 0.75, 1, 1]),
+                                         ((4, 4, 8), 2, [0.3, 1, 0.2, 0.8, 1, 0.6, 0.1, 0.9])])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_laminate_closed_form_gpu(n, axis, prof, prec):
+    rve = _rve()
+    phi = li.laminate_phi(n, axis, prof)
+    out = rve.solve(_dev(phi), C1, np.eye(6), precision=prec, tol=1e-10 if prec else 1e-7, want_stress=False)
+    ref = bf.laminate_closed_form(np.asarray(prof, dtype=np.float32), axis, 1.0, 0.3)
+    assert np.abs(out["eff_stress"].T - ref).max() < (1e-10 if prec else 1e-6)
+
+
+def test_homogeneous_and_empty_cells():
+    rve = _rve()
+    n = (8, 6, 4)
+    E = np.array([[1e-3, -2e-4, 3e-4, 1e-4, 0, 2e-4]])
+    c = float(np.float32(0.7))  # phi is an FP32 input
+    for prec in (0, 1):
+        out = rve.solve(_dev(np.full(n, c, np.float32)), C1, E, precision=prec)
+        assert out["status"] == 0 and out["iterations"][0] == 0
+        assert np.abs(out["eff_stress"][0] - c * C1 @ E[0]).max() < 1e-18
+        assert float(out["strain"].abs().max()) == 0.0
+        out = rve.solve(_dev(np.zeros(n, np.float32)), C1, E, precision=prec)
+        assert out["status"] == 0 and np.abs(out["eff_stress"]).max() == 0.0
+
+
+def test_warm_start_and_iteration_cap():
+    rve = _rve()
+    n = (16, 16, 16)
+    phi, _ = li.octet_phase_map(n, 0.15)
+    E = np.eye(6)[[0, 3]]
+    d = _dev(phi, torch.float32)
+    cold = rve.solve(d, C1, E, tol=1e-8)
+    assert cold["status"] == 0
+    # a start that already meets a looser tolerance needs no iteration
+    warm = rve.solve(d, C1, E, tol=1e-6, eps0=cold["strain"])
+    assert np.all(warm["iterations"] == 0) and warm["status"] == 0
+    assert _rel(warm["eff_stress"], cold["eff_stress"]) < 1e-6
+    # a perturbed start (its incompatible part is projected away) converges to the same answer
+    noisy = cold["strain"] + 1e-4 * torch.randn_like(cold["strain"])
+    w2 = rve.solve(d, C1, E, tol=1e-8, eps0=noisy)
+    assert w2["status"] == 0 and _rel(w2["eff_stress"], cold["eff_stress"]) < 1e-6
+    capped = rve.solve(d, C1, E, tol=1e-6, max_iter=5)
+    assert capped["status"] == rve.RVE_NOT_CONVERGED
+    assert np.all(capped["iterations"] == 5)
+
+
+def test_rejects_bad_phi_on_device():
+    rve = _rve()
+    n = (8, 8, 8)
+    bad = np.full(n, 0.5, np.float32)
+    bad[1, 2, 3] = np.nan
+    out = rve.solve(_dev(bad), C1, np.eye(6)[:1], check=False)
+    assert out["status"] == rve.RVE_ENONFINITE
+    bad[1, 2, 3] = 1.5
+    out = rve.solve(_dev(bad), C1, np.eye(6)[:1], check=False)
+    assert out["status"] == rve.RVE_EINVAL
+
+
+# ------------------------------------------------------------------ full-size properties (256^3)
+def _stencil_strain(u, L):
+    """Mandel centre strains of periodic nodal displacements u [3,*n] (8-corner stencil)."""
+    n = u.shape[1:]
+    h = [L[p] / n[p] for p in range(3)]
+    D = np.zeros((3, 3) + n)  # D[p, i] = d_p u_i at voxel centres
+    for p in range(3):
+        q, r = [a for a in range(3) if a != p]
+        acc = np.zeros((3,) + n)
+        for o1 in (0, 1):
+            for o2 in (0, 1):
+                s = u
+                if o1:
+                    s = np.roll(s, -1, axis=1 + q)
+                if o2:
+                    s = np.roll(s, -1, axis=1 + r)
+                acc += np.roll(s, -1, axis=1 + p) - s
+        D[p] = acc / (4 * h[p])
+    sq = np.sqrt(2.0)
+    return np.stack([D[0, 0], D[1, 1], D[2, 2], sq * 0.5 * (D[1, 2] + D[2, 1]), sq * 0.5 * (D[0, 2] + D[2, 0]),
+                     sq * 0.5 * (D[0, 1] + D[1, 0])])
+
+
+def test_full_size_operator_properties_256():
+    """At the 256^3 benchmark size: the projection fixes stencil strains and is idempotent and
+    self-adjoint; the stiffness round trip is exact."""
+    rve = _rve()
+    n = (256, 256, 256)
+    L = (1.0, 1.0, 1.0)
+    rng = np.random.default_rng(9)
+    u = rng.standard_normal((3,) + n).astype(np.float32)
+    Bu = _stencil_strain(u.astype(np.float64), L).astype(np.float32)
+    del u
+    y = rve.apply(_dev(Bu[None]), None, mode=rve.APPLY_PROJECTION).cpu().numpy()[0]
+    assert _rel(y, Bu) < 2e-5
+    del y
+    x = _dev(rng.standard_normal((1, 6) + n).astype(np.float32))
+    gx = rve.apply(x, None, mode=rve.APPLY_PROJECTION)
+    ggx = rve.apply(gx, None, mode=rve.APPLY_PROJECTION)
+    assert float((ggx - gx).abs().max() / gx.abs().max()) < 2e-5
+    z = _dev(rng.standard_normal((1, 6) + n).astype(np.float32))
+    gz = rve.apply(z, None, mode=rve.APPLY_PROJECTION)
+    a = float((gx.double() * z.double()).sum())
+    b = float((x.double() * gz.double()).sum())
+    assert abs(a - b) < 1e-5 * abs(a)
+
+
+def test_benchmark_workload_solution_properties():
+    """The 256^3 defect octet (15%, roughness, 200 pores), uniaxial strain, FP32-mixed, tol 1e-6:
+    the returned strain is compatible, the stress is equilibrated (Ghat sigma = 0) and the
+    residual recomputed in FP64 meets the tolerance."""
+    rve = _rve()
+    n = (256, 256, 256)
+    phi, info = li.octet_defect_phase_map(n, 0.15)
+    assert info.n_pores == 200
+    E = li.uniaxial_strain(1e-3)[None]
+    d = _dev(phi)
+    out = rve.solve(d, C1, E, tol=1e-6)
+    assert out["status"] == 0 and out["rel_residual"][0] <= 1e-6
+    eps = out["strain"]
+    geps = rve.apply(eps, None, mode=rve.APPLY_PROJECTION)
+    assert float((geps - eps).abs().max() / eps.abs().max()) < 1e-4
+    sig = out["stress"]
+    gsig = rve.apply(sig, None, mode=rve.APPLY_PROJECTION)
+    assert float(gsig.double().norm() / sig.double().norm()) < 1e-5
+    # FP64 residual with the FP64 kernels
+    b = -rve.apply(torch.full_like(eps, 0, dtype=torch.float64) + _dev(E, torch.float64)[:, :, None, None, None],
+                   d, C1)
+    r = b - rve.apply(eps.double(), d, C1)
+    assert float(r.norm() / b.norm()) < 2e-6
+    # Hill-Mandel: <sigma : eps~> = 0 for the exact solution; the approximate one leaves
+    # <Ghat sigma : eps~>, bounded by the residual: compare with the macroscopic work Ebar . <sigma>
+    hm = float((sig.double() * eps.double()).sum(dim=1).mean())
+    work = float(E[0] @ out["eff_stress"][0])
+    assert abs(hm) < 1e-4 * work
