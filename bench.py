@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--workload", default="octet256_defects")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1)
+    ap.add_argument("--inner-floor", type=float, default=None,
+                    help="FP32-mixed: relative reduction at which an inner FP32 sweep stops (library default 1e-5)")
     ap.add_argument("--precision", choices=["fp32-mixed", "fp64"], default=None,
                     help="override the workload's precision (fp64 = the plain FP64 GPU MINRES)")
     args = ap.parse_args()
@@ -110,8 +112,13 @@ def main():
     nvox = int(np.prod(n))
     nc = E.shape[0]
 
+    extra = {}
+    if args.inner_floor:
+        extra["inner_floor"] = args.inner_floor
+        cfg["inner_floor"] = args.inner_floor
+
     def one():
-        return rve.solve(d, C1, E, tol=cfg["tol"], precision=prec, workspace=ws, want_stress=True)
+        return rve.solve(d, C1, E, tol=cfg["tol"], precision=prec, workspace=ws, want_stress=True, **extra)
 
     for i in range(args.warmup):
         out = one()

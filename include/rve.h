@@ -66,12 +66,14 @@ typedef struct {
   int32_t scheme;       /* RVE_SCHEME_ROTATED (eq. freqrot, default) or RVE_SCHEME_CONTINUOUS (eq. freq) */
   int32_t check_every;  /* iterations between host checks of the convergence flags (>= 1) */
   double inner_floor;   /* FP32_MIXED: an inner FP32 sweep stops no later than at this fraction of its
-                           own starting residual (default 1e-5; in (0, 1)) */
+                           own starting residual (default 1e-3; in (0, 1)).  FP32 Lanczos on these
+                           near-singular operators cannot reduce its residual much further than
+                           ~1e-3 reliably; the FP64 refinement then restarts from the true residual */
   double inner_safety;  /* FP32_MIXED: an inner sweep aims at inner_safety * tol * ||b|| (default 0.5) */
 } rve_options;
 
-/* Fills *opt with the defaults: tol 1e-6, max_iter 5000, FP32_MIXED, max_refine 4, natural Nyquist,
- * rotated scheme, check_every 24, inner_floor 1e-5, inner_safety 0.5. */
+/* Fills *opt with the defaults: tol 1e-6, max_iter 5000, FP32_MIXED, max_refine 24, natural Nyquist,
+ * rotated scheme, check_every 24, inner_floor 1e-3, inner_safety 0.5. */
 void rve_default_options(rve_options* opt);
 
 /* 1 if the FFT kernels provide axis length n (n = NA*NB with radix factors 2, 3, 4, 5), else 0. */

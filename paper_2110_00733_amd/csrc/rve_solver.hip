@@ -524,7 +524,7 @@ struct Tables {
 // Workspace carve-out.  Sizes depend only on (grid, n_cases, precision).
 struct Layout {
   long long off_state, off_info, off_part, off_sums, off_tab32, off_tab64, off_u32[3], off_d32[2], off_x32,
-      off_spec32, off_x64, off_b64, off_r64, off_spec64, off_u64[3], off_d64[2], off_flag, total;
+      off_spec32, off_x64, off_b64, off_r64, off_t64, off_spec64, off_u64[3], off_d64[2], off_flag, total;
   int np_p5, np_vec, np_post;
 };
 
@@ -572,6 +572,7 @@ static Layout make_layout(const Plan& pl, int nc, int precision, bool solve) {
     L.off_x64 = take(8 * n6);
     L.off_b64 = take(8 * n6);
     L.off_r64 = take(8 * n6);
+    if (precision == RVE_FP32_MIXED) L.off_t64 = take(8 * n6);
   }
   L.total = o;
   return L;
@@ -779,11 +780,11 @@ void rve_default_options(rve_options* o) {
   o->tol = 1e-6;
   o->max_iter = 5000;
   o->precision = RVE_FP32_MIXED;
-  o->max_refine = 4;
+  o->max_refine = 24;
   o->nyquist = RVE_NYQ_NATURAL;
   o->scheme = RVE_SCHEME_ROTATED;
   o->check_every = 24;
-  o->inner_floor = 1e-5;
+  o->inner_floor = 1e-3;
   o->inner_safety = 0.5;
 }
 
@@ -990,6 +991,7 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
   double* x64 = reinterpret_cast<double*>(ws + L.off_x64);
   double* b64 = reinterpret_cast<double*>(ws + L.off_b64);
   double* r64 = reinterpret_cast<double*>(ws + L.off_r64);
+  double* t64 = reinterpret_cast<double*>(ws + L.off_t64);
   cx<double>* spec64 = reinterpret_cast<cx<double>*>(ws + L.off_spec64);
 
   // phi validity (device pre-pass)
@@ -1060,14 +1062,16 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
   double* Ed2 = sums;  // needs 6*nc doubles: sums holds 8*nc
   HIPCHK(hipMemcpyAsync(Ed2, macro_strain, sizeof(double) * 6 * nc, hipMemcpyHostToDevice, s));
 
+  // projection material: C = identity independent of phi
+  Material<double> ident64;
+  memset(&ident64, 0, sizeof(ident64));
+  for (int i = 0; i < 6; ++i) ident64.C0[i * 7] = 1.0;
+  ident64.has_c0 = 1;
+  ident64.use_phi = 0;
   // start: x64 = 0 or projected warm start; r64 = b - A x64
   if (eps0) {
     // x64 = Ghat eps0 (projection, C = identity)
-    Material<double> id;
-    memset(&id, 0, sizeof(id));
-    for (int i = 0; i < 6; ++i) id.C0[i * 7] = 1.0;
-    id.has_c0 = 1;
-    id.use_phi = 0;
+    const Material<double>& id = ident64;
     if (prec == RVE_FP32_MIXED) {
       hipLaunchKernelGGL((k_lincomb<float, double>), vg, vb, 0, s, r64, (const float*)eps0, 1.0,
                          (const double*)nullptr, 0.0, n6, part);
@@ -1116,6 +1120,11 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
       hipLaunchKernelGGL(k_sweep_done, dim3((nc + 63) / 64), dim3(64), 0, s, dst, dci, nc);
       // x64 += x32 ; r64 = b - A x64
       hipLaunchKernelGGL(k_accum<float>, vg, vb, 0, s, x64, B.x, n6, (const int*)nullptr);
+      // The exact fluctuation is compatible and has zero mean.  FP32 rounding inside the sweep leaves
+      // incompatible components (a mean among them) that the projected residual cannot see but the
+      // average stress does: project the FP64 iterate back onto compatible fields.
+      apply_op<double>(pl, nc, x64, nullptr, phi, ident64, tb64, spec64, t64, nullptr, nullptr, nullptr, 0, s);
+      std::swap(x64, t64);
       apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, 0, s);
       hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
       hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
