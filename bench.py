@@ -65,13 +65,12 @@ def algorithmic_bytes(kind, n, nc, elem):
     spec = 6 * (n2 // 2 + 1) * n0 * n1 * 2 * elem
     field = 6 * nv * elem
     table = {
-        "P1_stiffness_fft_axis2": field + 4 * nv + spec,
+        "P1_stiffness_fft_axis2_alpha": field + 4 * nv + spec,   # u_k, phi -> spectrum
         "P2_fft_axis1": 2 * spec,
         "P3_fft_axis0_projection": 2 * spec,
         "P4_ifft_axis1": 2 * spec,
-        "P5_ifft_axis2_dot": spec + 2 * field,
-        "U1_lanczos_update": 4 * field,
-        "U2_direction_update": 6 * field,
+        "P5_ifft_axis2_lanczos": spec + 3 * field,        # spectrum, u_k, u_k-1 -> u_k+1
+        "U2_direction_update": 6 * field,                        # u_k, d_k-1, d_k-2, x -> d_k, x
     }
     return table.get(kind, 0) * nc
 

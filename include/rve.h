@@ -66,14 +66,14 @@ typedef struct {
   int32_t scheme;       /* RVE_SCHEME_ROTATED (eq. freqrot, default) or RVE_SCHEME_CONTINUOUS (eq. freq) */
   int32_t check_every;  /* iterations between host checks of the convergence flags (>= 1) */
   double inner_floor;   /* FP32_MIXED: an inner FP32 sweep stops no later than at this fraction of its
-                           own starting residual (default 1e-3; in (0, 1)).  FP32 Lanczos on these
-                           near-singular operators cannot reduce its residual much further than
-                           ~1e-3 reliably; the FP64 refinement then restarts from the true residual */
+                           own starting residual (default 3e-2; in (0, 1)).  FP32 Lanczos on these
+                           near-singular operators stalls when asked for much deeper reductions; the
+                           FP64 refinement restarts from the true residual instead */
   double inner_safety;  /* FP32_MIXED: an inner sweep aims at inner_safety * tol * ||b|| (default 0.5) */
 } rve_options;
 
 /* Fills *opt with the defaults: tol 1e-6, max_iter 5000, FP32_MIXED, max_refine 24, natural Nyquist,
- * rotated scheme, check_every 24, inner_floor 1e-3, inner_safety 0.5. */
+ * rotated scheme, check_every 24, inner_floor 3e-2, inner_safety 0.5. */
 void rve_default_options(rve_options* opt);
 
 /* 1 if the FFT kernels provide axis length n (n = NA*NB with radix factors 2, 3, 4, 5), else 0. */
@@ -122,9 +122,9 @@ rve_status rve_apply(const rve_grid* grid, const float* voxel_fraction_field, co
 /* Optional per-kernel timing (instrumentation for benchmarks, not on by default).  When enabled,
  * every kernel launched inside the MINRES iteration loop of solve_rve is bracketed by HIP events
  * recorded on the solve stream; elapsed times are accumulated per kernel kind at the host's
- * convergence checks.  Kinds, in order: P1 stiffness + FFT axis 2, P2 FFT axis 1, P3 FFT axis 0 +
- * projection + inverse, P4 inverse FFT axis 1, P5 inverse FFT axis 2 + dot partials, S1 Lanczos
- * alpha, U1 Lanczos update, S2 Givens step, U2 direction + solution update.
+ * convergence checks.  Kinds, in order: P1 stiffness + FFT axis 2 (+ Lanczos alpha), P2 FFT axis 1,
+ * P3 FFT axis 0 + projection + inverse, P4 inverse FFT axis 1, P5 inverse FFT axis 2 + Lanczos
+ * update, S1 Lanczos alpha, S2 Givens step, U2 direction + solution update.
  * rve_profile_read fills total milliseconds and launch counts for up to max_kinds kinds and
  * returns the number of kinds.  Not thread-safe with concurrent solves. */
 void rve_profile_enable(int32_t on);

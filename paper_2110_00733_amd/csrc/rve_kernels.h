@@ -58,12 +58,78 @@ __device__ __forceinline__ long long spec_idx(const GridDims& g, int cs, int k2,
   return ((((long long)cs * g.k2 + k2) * 6 + c) * g.n0 + n0) * (long long)g.n1 + n1;
 }
 
+// ---------------------------------------------------------------------------- Krylov scalar steps
+// (run by single-block kernels after P1 and P5: per-block partials are summed in a fixed order, so the
+// reductions are deterministic; device-wide fences inside the streaming kernels would write back the
+// whole L2 of every XCD and cost far more than a separate launch)
+__device__ __forceinline__ double sum_partials(const double* p, int np, double* red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += p[i];
+  return block_sum(acc, red);
+}
+
+// Lanczos diagonal from sum = <u_k, C u_k> * ib_k:  alpha_k = <v_k, A v_k> = <v_k, C v_k> for a compatible
+// v_k (Ghat is an orthogonal projector, so <v, Ghat C v> = <Ghat v, C v>).  Coefficients of the three-
+// term update u_{k+1} = A v_k - alpha_k v_k - beta_k v_{k-1} on the stored (unscaled) u vectors.
+__device__ __forceinline__ void alpha_step(MinresState& S, double sum) {
+  const double alpha = S.ib * sum;
+  S.alpha = alpha;
+  S.cu_v = alpha * S.ib;
+  S.cu_vp = S.beta * S.ib_prev;
+}
+
+// beta_{k+1} = ||u_{k+1}||; Givens QR step of the extended tridiagonal matrix; residual recurrence
+// |phibar|; coefficients of d_k = (v_k - delta_k d_{k-1} - eps_k d_{k-2}) / gamma_k and x += tau d_k.
+__device__ __forceinline__ void givens_step(MinresState& S, double sumsq) {
+  const double beta_next = sqrt(sumsq);
+  const double alpha = S.alpha, beta = S.beta;
+  const double eps = S.s2 * beta, dtil = S.c2 * beta;
+  const double delta = S.c1 * dtil + S.s1 * alpha;
+  const double gtil = -S.s1 * dtil + S.c1 * alpha;
+  const double gamma = hypot(gtil, beta_next);
+  S.iter += 1;
+  if (!(isfinite(alpha) && isfinite(beta_next) && isfinite(gamma))) {
+    S.status = -3;  // non-finite scalar
+    S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = 0.0;
+    S.finish = 1;
+    return;
+  }
+  if (gamma == 0.0) {
+    S.status = 2;  // breakdown
+    S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = 0.0;
+    S.finish = 1;
+    return;
+  }
+  const double c = gtil / gamma, sn = beta_next / gamma;
+  const double tau = c * S.phibar;
+  S.phibar = -sn * S.phibar;
+  S.cd_u = S.ib / gamma;
+  S.cd_d1 = -delta / gamma;
+  S.cd_d2 = -eps / gamma;
+  S.cx = tau;
+  S.c2 = S.c1;
+  S.s2 = S.s1;
+  S.c1 = c;
+  S.s1 = sn;
+  S.ib_prev = S.ib;
+  S.ib = beta_next > 0 ? 1.0 / beta_next : 0.0;
+  S.beta = beta_next;
+  if (fabs(S.phibar) <= S.tol_abs || beta_next == 0.0) {
+    S.finish = 1;
+  } else if (S.iter >= S.max_iter) {
+    S.status = 1;  // not converged
+    S.finish = 1;
+  }
+}
+
 // ============================================================================ P1
 // grid (ceil(N1/W), N0, ncases), block W*NB threads, dyn. LDS W*max(NA*(NB+1), N+1) complex
+// With `partials` (MINRES iterations): per-block <x, sigma> partials for the Lanczos alpha.
 template <typename T, int NA, int NB>
-__global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib, int xscale_stride,
-                            const float* __restrict__ phi, Material<T> mat, cx<T>* __restrict__ spec,
-                            const cx<T>* __restrict__ tw, GridDims g, int W, const MinresState* __restrict__ st) {
+__global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib,
+                                                   int xscale_stride, const float* __restrict__ phi, Material<T> mat,
+                                                   cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, GridDims g,
+                                                   int W, const MinresState* __restrict__ st, double* partials) {
   constexpr int N = NA * NB;
   constexpr int TT = NB;
   constexpr int CB = (NA + TT - 1) / TT;
@@ -80,6 +146,8 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
   const T xs = xscale_ib ? (T)xscale_ib[(long long)cs * xscale_stride] : (T)1;
   const long long row = ((long long)n0 * g.n1 + n1) * N;
   const T* xc = x + (long long)cs * 6 * g.nvox;
+  __shared__ double red[16];
+  double acc = 0.0;
 
   T sg[6][NA];
   {
@@ -94,18 +162,24 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
     for (int i = 0; i < NA; ++i) {
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
-        T acc = 0;
+        T sv = 0;
         if (mat.use_phi) {
 #pragma unroll
-          for (int b = 0; b < 6; ++b) acc += mat.Cd[a * 6 + b] * e[b][i];
-          acc *= ph[i];
+          for (int b = 0; b < 6; ++b) sv += mat.Cd[a * 6 + b] * e[b][i];
+          sv *= ph[i];
         }
         if (mat.has_c0) {
 #pragma unroll
-          for (int b = 0; b < 6; ++b) acc += mat.C0[a * 6 + b] * e[b][i];
+          for (int b = 0; b < 6; ++b) sv += mat.C0[a * 6 + b] * e[b][i];
         }
-        sg[a][i] = acc * xs;
+        sg[a][i] = sv * xs;
       }
+    }
+    if (partials) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) acc += (double)e[a][i] * (double)sg[a][i];
     }
   }
   const int ws = tid % W, m = tid / W, M = blockDim.x / W;
@@ -152,6 +226,11 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
         spec[spec_idx(g, cs, k, 2 * pr + 1, n0, n1s)] = B;
       }
     }
+  }
+  if (partials) {
+    const unsigned nb = gridDim.x * gridDim.y;
+    const double sblk = block_sum(acc, red);
+    if (tid == 0) partials[(long long)cs * nb + blockIdx.y * gridDim.x + blockIdx.x] = sblk;
   }
 }
 
@@ -201,10 +280,11 @@ __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, const c
 // grid (ceil(N1/W), K2, ncases), block W*NB threads, dyn. LDS NA*(NB*W+1) complex
 // All six components of the thread's pencil elements are loaded up front (maximum loads in flight)
 // and transformed in place in one register array D[c][.]: stage-A layout D[c][i] = x[t + NB i],
-// stage-B layout D[c][j*NB + b] = X[a_j + NA b] with a_j = t + NB j.
-template <typename T, int NA, int NB>
+// stage-B layout D[c][j*NB + b] = X[a_j + NA b] with a_j = t + NB j.  IDENT replaces the projection
+// by the identity (test mode of the stiffness/transform round trip).
+template <typename T, int NA, int NB, bool IDENT>
 __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw,
-                                                       FreqTables<T> ft, GridDims g, int W, T inv_total, int identity,
+                                                       FreqTables<T> ft, GridDims g, int W, T inv_total,
                                                        const MinresState* __restrict__ st) {
   constexpr int N = NA * NB;
   constexpr int TT = NB;
@@ -262,7 +342,7 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
       for (int b = 0; b < NB; ++b) {
         const int e = j * NB + b;
         const int k0 = a + NA * b;
-        if (identity) {
+        if (IDENT) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) D[c][e] = scl(D[c][e], inv_total);
         } else {
@@ -331,11 +411,13 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
 
 // ============================================================================ P5
 // grid (ceil(N1/W), N0, ncases), block W*NB threads, dyn. LDS W*max(NA*(NB+1), N+1) complex
-// partials[(cs*N0 + n0)*gridDim.x + blockIdx.x] = sum over the block of <y, dotv> (if dotv)
+// Lanczos mode (uk != nullptr, MINRES iterations): the transform output p = A v_k is never stored;
+// instead y = u_{k+1} = p - cu_v u_k - cu_vp u_{k-1} is written with per-block ||u_{k+1}||^2 partials.
 template <typename T, int NA, int NB>
-__global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spec, T* __restrict__ y, const T* __restrict__ dotv,
-                            double* __restrict__ partials, const cx<T>* __restrict__ tw, GridDims g, int W,
-                            const MinresState* __restrict__ st) {
+__global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spec, T* __restrict__ y,
+                                                   const T* __restrict__ uk, const T* __restrict__ ukm1,
+                                                   double* partials, const cx<T>* __restrict__ tw, GridDims g, int W,
+                                                   const MinresState* __restrict__ st) {
   constexpr int N = NA * NB;
   constexpr int TT = NB;
   constexpr int CB = (NA + TT - 1) / TT;
@@ -354,7 +436,10 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
   const int n1s = n1_0 + ws;
   const long long row = ((long long)n0 * g.n1 + n1) * N;
   T* yc = y + (long long)cs * 6 * g.nvox;
-  const T* dc = dotv ? dotv + (long long)cs * 6 * g.nvox : nullptr;
+  const bool lz = uk != nullptr;
+  const T* uc = lz ? uk + (long long)cs * 6 * g.nvox : nullptr;
+  const T* umc = lz ? ukm1 + (long long)cs * 6 * g.nvox : nullptr;
+  const T cv = lz ? (T)st[cs].cu_v : (T)0, cvp = lz ? (T)st[cs].cu_vp : (T)0;
   double acc = 0.0;
   // all six spectrum components this thread gathers, loaded up front
   constexpr int LK = (N / 2 + 1 + TT - 1) / TT;
@@ -368,17 +453,20 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
   }
 #pragma unroll
   for (int pr = 0; pr < 3; ++pr) {
-    // operand of the dot product for this pair, fetched early
+    // Lanczos operands for this pair (combination c u_k + c' u_{k-1}), fetched early
     T dv[CB][NB][2];
-    if (dc && row_ok) {
+    if (lz && row_ok) {
 #pragma unroll
       for (int j = 0; j < CB; ++j) {
         const int a = t + TT * j;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const long long o = row + a + NA * b;
-          dv[j][b][0] = (a < NA) ? dc[(2 * pr) * g.nvox + o] : (T)0;
-          dv[j][b][1] = (a < NA) ? dc[(2 * pr + 1) * g.nvox + o] : (T)0;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const long long oo = (2 * pr + h) * g.nvox + o;
+            dv[j][b][h] = (CB == 1 || a < NA) ? cv * uc[oo] + cvp * umc[oo] : (T)0;
+          }
         }
       }
     }
@@ -422,17 +510,23 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
             const long long o = row + a + NA * b;
-            yc[(2 * pr) * g.nvox + o] = yb[b].re;
-            yc[(2 * pr + 1) * g.nvox + o] = yb[b].im;
-            if (dc) acc += (double)yb[b].re * (double)dv[j][b][0] + (double)yb[b].im * (double)dv[j][b][1];
+            T r0 = yb[b].re, r1 = yb[b].im;
+            if (lz) {
+              r0 -= dv[j][b][0];
+              r1 -= dv[j][b][1];
+              acc += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+            }
+            yc[(2 * pr) * g.nvox + o] = r0;
+            yc[(2 * pr + 1) * g.nvox + o] = r1;
           }
         }
       }
     }
   }
-  if (partials) {
-    const double s = block_sum(acc, red);
-    if (tid == 0) partials[((long long)cs * g.n0 + n0) * gridDim.x + blockIdx.x] = s;
+  if (lz) {
+    const unsigned nb = gridDim.x * gridDim.y;
+    const double sblk = block_sum(acc, red);
+    if (tid == 0) partials[(long long)cs * nb + blockIdx.y * gridDim.x + blockIdx.x] = sblk;
   }
 }
 

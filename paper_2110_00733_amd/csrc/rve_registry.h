@@ -6,19 +6,20 @@ namespace rve {
 
 template <typename T>
 using P1Fn = void (*)(const T*, const double*, int, const float*, Material<T>, cx<T>*, const cx<T>*, GridDims, int,
-                      const MinresState*);
+                      const MinresState*, double*);
 template <typename T>
 using P2Fn = void (*)(cx<T>*, const cx<T>*, GridDims, int, long long, const MinresState*);
 template <typename T>
-using P3Fn = void (*)(cx<T>*, const cx<T>*, FreqTables<T>, GridDims, int, T, int, const MinresState*);
+using P3Fn = void (*)(cx<T>*, const cx<T>*, FreqTables<T>, GridDims, int, T, const MinresState*);
 template <typename T>
-using P5Fn = void (*)(const cx<T>*, T*, const T*, double*, const cx<T>*, GridDims, int, const MinresState*);
+using P5Fn = void (*)(const cx<T>*, T*, const T*, const T*, double*, const cx<T>*, GridDims, int,
+                      const MinresState*);
 
 template <typename T>
 struct LenKernels {
   P1Fn<T> p1;
   P2Fn<T> p2f, p2i;
-  P3Fn<T> p3;
+  P3Fn<T> p3, p3_ident;
   P5Fn<T> p5;
 };
 
@@ -41,6 +42,7 @@ const LenEntry* find_len(int n);
 
 #define RVE_LEN_KERNELS(T_, NA_, NB_)                                                                  \
   {&rve::k_fwd_axis2<T_, NA_, NB_>, &rve::k_axis1<T_, NA_, NB_, -1>, &rve::k_axis1<T_, NA_, NB_, 1>, \
-   &rve::k_axis0_project<T_, NA_, NB_>, &rve::k_inv_axis2<T_, NA_, NB_>}
+   &rve::k_axis0_project<T_, NA_, NB_, false>, &rve::k_axis0_project<T_, NA_, NB_, true>,              \
+   &rve::k_inv_axis2<T_, NA_, NB_>}
 #define RVE_LEN_ENTRY(N_, NA_, NB_) \
   rve::LenEntry { N_, NA_, NB_, RVE_LEN_KERNELS(float, NA_, NB_), RVE_LEN_KERNELS(double, NA_, NB_) }

@@ -1,10 +1,12 @@
 // Host driver and Krylov kernels of the gfx950 Galerkin-FFT homogenization solver (C ABI in rve.h).
 //
-// One MINRES iteration is ten launches, all on one stream, no host involvement:
-//   P1..P5 (operator pass kernels, rve_kernels.h) -> S1 Lanczos alpha -> U1 Lanczos vector update
-//   -> S2 Givens QR step + convergence test -> U2 search direction + solution update.
+// One MINRES iteration is eight launches on one stream, no host involvement:
+//   P1 stiffness + FFT axis 2, with per-block partials of alpha = <v, C v>;  S1 alpha (one block)
+//   P2, P3 (projection), P4 transforms
+//   P5 inverse FFT axis 2 fused with the Lanczos three-term update and ||u_{k+1}||^2 partials
+//   S2 Givens QR step + convergence test (one block);  U2 search direction + solution update.
 // Vectors carry a deferred normalisation: the Lanczos vector v_k is stored unscaled (u_k) and its
-// 1/beta_k is applied inside the consumers (P1 stiffness, U1, U2).
+// 1/beta_k is applied inside the consumers (P1 stiffness, P5 update, U2).
 // FP32_MIXED: fields and transforms in FP32, Krylov scalars and all inner products in FP64; the
 // outer loop recomputes the true residual with FP64 operator kernels and refines (x64 += delta).
 #include <hip/hip_runtime.h>
@@ -48,10 +50,10 @@ static void ensure_registry() {
 // Optional HIP-event timing of every launch inside the MINRES iteration loop (on the solve stream).
 // Events come from a pool created on first enable; pairs are read back at the host's chunk syncs.
 namespace prof {
-enum Kind { P1 = 0, P2, P3, P4, P5, S1, U1, S2, U2, NKIND };
-static const char* kNames[NKIND] = {"P1_stiffness_fft_axis2", "P2_fft_axis1", "P3_fft_axis0_projection",
-                                    "P4_ifft_axis1", "P5_ifft_axis2_dot", "S1_lanczos_alpha",
-                                    "U1_lanczos_update", "S2_givens", "U2_direction_update"};
+enum Kind { P1 = 0, P2, P3, P4, P5, S1, S2, U2, NKIND };
+static const char* kNames[NKIND] = {"P1_stiffness_fft_axis2_alpha", "P2_fft_axis1", "P3_fft_axis0_projection",
+                                    "P4_ifft_axis1", "P5_ifft_axis2_lanczos", "S1_alpha", "S2_givens",
+                                    "U2_direction_update"};
 static bool on = false;
 static std::vector<hipEvent_t> pool;
 static std::vector<std::pair<int, int>> pending;
@@ -213,31 +215,9 @@ __global__ void k_minres_init(MinresState* st, const double* partials, int np, C
     S.cu_v = S.cu_vp = S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = 0.0;
     S.iter = 0;
     S.max_iter = max_iter - ci[cs].iters;
-    S.done = 0;
     S.status = 0;
     S.finish = (!ci[cs].active || beta <= S.tol_abs || S.max_iter <= 0) ? 1 : 0;
-  }
-}
-
-// S1: alpha_k = <A v_k, v_k> = ib_k * <p, u_k>; Lanczos coefficients for U1.
-__global__ void k_minres_alpha(MinresState* st, const double* partials, int np) {
-  __shared__ double red[16];
-  const int cs = blockIdx.x;
-  MinresState& S = st[cs];
-  if (S.done) return;
-  if (S.finish) {
-    __syncthreads();
-    if (threadIdx.x == 0) S.done = 1;
-    return;
-  }
-  double acc = 0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[(long long)cs * np + i];
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) {
-    const double alpha = S.ib * s;
-    S.alpha = alpha;
-    S.cu_v = alpha * S.ib;
-    S.cu_vp = S.beta * S.ib_prev;
+    S.done = 0;
   }
 }
 
@@ -256,94 +236,30 @@ struct Vec16<double> {
   static constexpr int n = 2;
 };
 
-// U1: p <- p - cu_v u_k - cu_vp u_{k-1} (= beta_{k+1} v_{k+1}), partial sums of p^2.
-template <typename T, bool VEC>
-__global__ __launch_bounds__(256) void k_lanczos(T* p, const T* uk, const T* ukm1, const MinresState* st,
-                                                 long long n6, double* partials) {
+// S1: alpha_k from the P1 partials (fixed-order sum).  Also retires a case whose previous iteration
+// finished (that iteration's U2 has run by now).
+__global__ void k_minres_alpha(MinresState* st, const double* partials, int np) {
   __shared__ double red[16];
-  const int cs = blockIdx.y;
-  const MinresState& S = st[cs];
+  const int cs = blockIdx.x;
+  MinresState& S = st[cs];
   if (S.done) return;
-  const T a = (T)S.cu_v, b = (T)S.cu_vp;
-  const long long off = (long long)cs * n6;
-  double acc = 0;
-  constexpr int V = VEC ? Vec16<T>::n : 1;
-  using VT = typename Vec16<T>::type;
-  const long long nv = n6 / V;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
-    if constexpr (VEC) {
-      VT pv = reinterpret_cast<const VT*>(p + off)[i];
-      const VT uv = reinterpret_cast<const VT*>(uk + off)[i];
-      const VT wv = reinterpret_cast<const VT*>(ukm1 + off)[i];
-      T* pe = reinterpret_cast<T*>(&pv);
-      const T* ue = reinterpret_cast<const T*>(&uv);
-      const T* we = reinterpret_cast<const T*>(&wv);
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        pe[e] = pe[e] - a * ue[e] - b * we[e];
-        acc += (double)pe[e] * (double)pe[e];
-      }
-      reinterpret_cast<VT*>(p + off)[i] = pv;
-    } else {
-      const T v = p[off + i] - a * uk[off + i] - b * ukm1[off + i];
-      p[off + i] = v;
-      acc += (double)v * (double)v;
-    }
+  if (S.finish) {
+    __syncthreads();
+    if (threadIdx.x == 0) S.done = 1;
+    return;
   }
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[(long long)cs * gridDim.x + blockIdx.x] = s;
+  const double s = sum_partials(partials + (long long)cs * np, np, red);
+  if (threadIdx.x == 0) alpha_step(S, s);
 }
 
-// S2: beta_{k+1}; QR of the extended tridiagonal matrix by Givens rotations; residual recurrence.
+// S2: beta_{k+1} from the P5 partials, Givens step, convergence test.
 __global__ void k_minres_givens(MinresState* st, const double* partials, int np) {
   __shared__ double red[16];
   const int cs = blockIdx.x;
   MinresState& S = st[cs];
   if (S.done) return;
-  double acc = 0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[(long long)cs * np + i];
-  const double s = block_sum(acc, red);
-  if (threadIdx.x != 0) return;
-  const double beta_next = sqrt(s);
-  const double alpha = S.alpha, beta = S.beta;
-  const double eps = S.s2 * beta, dtil = S.c2 * beta;
-  const double delta = S.c1 * dtil + S.s1 * alpha;
-  const double gtil = -S.s1 * dtil + S.c1 * alpha;
-  const double gamma = hypot(gtil, beta_next);
-  S.iter += 1;
-  if (!(isfinite(alpha) && isfinite(beta_next) && isfinite(gamma))) {
-    S.status = RVE_ENONFINITE;
-    S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = 0.0;
-    S.finish = 1;
-    return;
-  }
-  if (gamma == 0.0) {
-    S.status = RVE_BREAKDOWN;
-    S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = 0.0;
-    S.finish = 1;
-    return;
-  }
-  const double c = gtil / gamma, sn = beta_next / gamma;
-  const double tau = c * S.phibar;
-  S.phibar = -sn * S.phibar;
-  S.cd_u = S.ib / gamma;
-  S.cd_d1 = -delta / gamma;
-  S.cd_d2 = -eps / gamma;
-  S.cx = tau;
-  S.c2 = S.c1;
-  S.s2 = S.s1;
-  S.c1 = c;
-  S.s1 = sn;
-  S.ib_prev = S.ib;
-  S.ib = beta_next > 0 ? 1.0 / beta_next : 0.0;
-  S.beta = beta_next;
-  const bool conv = fabs(S.phibar) <= S.tol_abs || beta_next == 0.0;
-  if (conv) {
-    S.finish = 1;
-  } else if (S.iter >= S.max_iter) {
-    S.status = RVE_NOT_CONVERGED;
-    S.finish = 1;
-  }
+  const double s = sum_partials(partials + (long long)cs * np, np, red);
+  if (threadIdx.x == 0) givens_step(S, s);
 }
 
 // U2: d_k = cd_u u_k + cd_d1 d_{k-1} + cd_d2 d_{k-2} (written over d_{k-2}); x += cx d_k.
@@ -623,11 +539,13 @@ static Material<T> make_material(const double* Cvoid, const double* Csolid) {
 }
 
 // ---------------------------------------------------------------------------- operator apply
-// y = F^{-1}{ Ghat : F{ C(x) : xs * x } } for nc cases.  dotv/partials: optional <y, dotv> partials.
+// y = F^{-1}{ Ghat : F{ C(x) : xs * x } } for nc cases.
+// Lanczos mode (uk != nullptr): P1 also forms alpha, P5 writes u_{k+1} instead of A x and performs the
+// Givens step (see rve_kernels.h); the partials buffer is then required.
 template <typename T>
 static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, const float* phi,
-                     const Material<T>& mat, const Tables<T>& tb, cx<T>* spec, T* y, const T* dotv, double* partials,
-                     const MinresState* st, int identity, hipStream_t s) {
+                     const Material<T>& mat, const Tables<T>& tb, cx<T>* spec, T* y, const T* uk, const T* ukm1,
+                     double* partials, MinresState* st, int identity, hipStream_t s) {
   const GridDims& g = pl.g;
   const LenKernels<T>& K0 = pl.ax[0]->k<T>();
   const LenKernels<T>& K1 = pl.ax[1]->k<T>();
@@ -644,7 +562,12 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     dim3 grid((g.n1 + W - 1) / W, g.n0, nc);
     prof::begin(prof::P1, s);
     hipLaunchKernelGGL(K2.p1, grid, dim3(W * nb2), lds, s, x, xscale, (int)(sizeof(MinresState) / sizeof(double)),
-                       phi, mat, spec, tb.tw[2], g, W, st);
+                       phi, mat, spec, tb.tw[2], g, W, st, uk ? partials : nullptr);
+    prof::end(s);
+    if (uk) {
+      prof::begin(prof::S1, s);
+      hipLaunchKernelGGL(k_minres_alpha, dim3(nc), dim3(256), 0, s, st, partials, (int)(grid.x * grid.y));
+    }
     prof::end(s);
   }
   // P2
@@ -668,8 +591,8 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     }
     dim3 grid((g.n1 + W - 1) / W, g.k2, nc);
     prof::begin(prof::P3, s);
-    hipLaunchKernelGGL(K0.p3, grid, dim3(W * nb0), lds, s, spec, tb.tw[0], ft, g, W, (T)(1.0 / (double)g.nvox),
-                       identity, st);
+    hipLaunchKernelGGL(identity ? K0.p3_ident : K0.p3, grid, dim3(W * nb0), lds, s, spec, tb.tw[0], ft, g, W,
+                       (T)(1.0 / (double)g.nvox), st);
     prof::end(s);
   }
   // P4
@@ -687,7 +610,12 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     const size_t lds = sizeof(cx<T>) * W * std::max(na2 * (nb2 + 1), N2 + 1);
     dim3 grid((g.n1 + W - 1) / W, g.n0, nc);
     prof::begin(prof::P5, s);
-    hipLaunchKernelGGL(K2.p5, grid, dim3(W * nb2), lds, s, spec, y, dotv, partials, tb.tw[2], g, W, st);
+    hipLaunchKernelGGL(K2.p5, grid, dim3(W * nb2), lds, s, spec, y, uk, ukm1, partials, tb.tw[2], g, W, st);
+    prof::end(s);
+    if (uk) {
+      prof::begin(prof::S2, s);
+      hipLaunchKernelGGL(k_minres_givens, dim3(nc), dim3(256), 0, s, st, partials, (int)(grid.x * grid.y));
+    }
     prof::end(s);
   }
 }
@@ -718,7 +646,6 @@ template <typename T>
 static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const float* phi, const Material<T>& mat,
                               const Tables<T>& tb, cx<T>* spec, MinresState* st, double* part, int max_iter,
                               int check, hipStream_t s) {
-  const int np_p5 = partials_p5(pl, (int)sizeof(T));
   const long long n6 = 6 * pl.g.nvox;
   dim3 vg, vb;
   vec_grid(nc, &vg, &vb);
@@ -731,19 +658,7 @@ static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const fl
   while (it < max_iter) {
     const int chunk = std::min(check, max_iter - it);
     for (int j = 0; j < chunk; ++j) {
-      apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], part, st, 0, s);
-      prof::begin(prof::S1, s);
-      hipLaunchKernelGGL(k_minres_alpha, dim3(nc), dim3(kThreads), 0, s, st, part, np_p5);
-      prof::end(s);
-      prof::begin(prof::U1, s);
-      if (vec)
-        hipLaunchKernelGGL((k_lanczos<T, true>), vg, vb, 0, s, B.u[ic], B.u[ib], B.u[ia], st, n6, part);
-      else
-        hipLaunchKernelGGL((k_lanczos<T, false>), vg, vb, 0, s, B.u[ic], B.u[ib], B.u[ia], st, n6, part);
-      prof::end(s);
-      prof::begin(prof::S2, s);
-      hipLaunchKernelGGL(k_minres_givens, dim3(nc), dim3(kThreads), 0, s, st, part, kRedBlocks);
-      prof::end(s);
+      apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s);
       prof::begin(prof::U2, s);
       if (vec)
         hipLaunchKernelGGL((k_direction<T, true>), vg, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
@@ -784,7 +699,7 @@ void rve_default_options(rve_options* o) {
   o->nyquist = RVE_NYQ_NATURAL;
   o->scheme = RVE_SCHEME_ROTATED;
   o->check_every = 24;
-  o->inner_floor = 1e-3;
+  o->inner_floor = 3e-2;
   o->inner_safety = 0.5;
 }
 
@@ -946,7 +861,7 @@ rve_status rve_apply(const rve_grid* grid, const float* phi, const double* phase
       mat.use_phi = 0;
     }
     apply_op<float>(pl, n_cases, (const float*)x, nullptr, phi, mat, tb, (cx<float>*)(ws + L.off_spec32), (float*)y,
-                    nullptr, nullptr, nullptr, mode == RVE_APPLY_STIFFNESS_ROUNDTRIP, s);
+                    nullptr, nullptr, nullptr, nullptr, mode == RVE_APPLY_STIFFNESS_ROUNDTRIP, s);
   } else {
     rve_status r = build_tables<double>(pl, grid, ws + L.off_tab64, scheme, nyquist, s);
     if (r != RVE_OK) return r;
@@ -958,7 +873,7 @@ rve_status rve_apply(const rve_grid* grid, const float* phi, const double* phase
       mat.use_phi = 0;
     }
     apply_op<double>(pl, n_cases, (const double*)x, nullptr, phi, mat, tb, (cx<double>*)(ws + L.off_spec64),
-                     (double*)y, nullptr, nullptr, nullptr, mode == RVE_APPLY_STIFFNESS_ROUNDTRIP, s);
+                     (double*)y, nullptr, nullptr, nullptr, nullptr, mode == RVE_APPLY_STIFFNESS_ROUNDTRIP, s);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -1022,7 +937,7 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
   vec_grid(nc, &vg, &vb);
   // b = -A(Ebar)   (FP64 operator)
   hipLaunchKernelGGL(k_fill_const<double>, vg, vb, 0, s, x64, Ed, g.nvox);
-  apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, 0, s);
+  apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, nullptr, 0, s);
   std::vector<double> hE(macro_strain, macro_strain + 6 * nc);
   // ||b||: b = -r64
   hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, b64, r64, -1.0, (const double*)nullptr, 0.0, n6,
@@ -1079,8 +994,8 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
       hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, (const double*)eps0, 1.0,
                          (const double*)nullptr, 0.0, n6, part);
     }
-    apply_op<double>(pl, nc, r64, nullptr, phi, id, tb64, spec64, x64, nullptr, nullptr, nullptr, 0, s);
-    apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, 0, s);
+    apply_op<double>(pl, nc, r64, nullptr, phi, id, tb64, spec64, x64, nullptr, nullptr, nullptr, nullptr, 0, s);
+    apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, nullptr, 0, s);
     hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
     hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
@@ -1123,9 +1038,9 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
       // The exact fluctuation is compatible and has zero mean.  FP32 rounding inside the sweep leaves
       // incompatible components (a mean among them) that the projected residual cannot see but the
       // average stress does: project the FP64 iterate back onto compatible fields.
-      apply_op<double>(pl, nc, x64, nullptr, phi, ident64, tb64, spec64, t64, nullptr, nullptr, nullptr, 0, s);
+      apply_op<double>(pl, nc, x64, nullptr, phi, ident64, tb64, spec64, t64, nullptr, nullptr, nullptr, nullptr, 0, s);
       std::swap(x64, t64);
-      apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, 0, s);
+      apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, nullptr, 0, s);
       hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
       hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
       hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
@@ -1148,7 +1063,7 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
     r = minres_loop<double>(pl, nc, B, phi, mat64, tb64, spec64, dst, part, opt->max_iter, check, s);
     if (r != RVE_OK) return r;
     hipLaunchKernelGGL(k_sweep_done, dim3((nc + 63) / 64), dim3(64), 0, s, dst, dci, nc);
-    apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, 0, s);
+    apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, nullptr, 0, s);
     hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
     hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
