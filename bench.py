@@ -75,6 +75,46 @@ def algorithmic_bytes(kind, n, nc, elem):
     return table.get(kind, 0) * nc
 
 
+KIND_TO_KERNEL = {  # profiler kind -> rocprofv3 kernel name prefix (FP32 fields)
+    "P1_stiffness_fft_axis2_alpha": "rve::k_fwd_axis2<{t},",
+    "P2_fft_axis1": "rve::k_axis1<{t},*,-1>",
+    "P3_fft_axis0_projection": "rve::k_axis0_project<{t},",
+    "P4_ifft_axis1": "rve::k_axis1<{t},*,1>",
+    "P5_ifft_axis2_lanczos": "rve::k_inv_axis2<{t},",
+    "U2_direction_update": "rve::k_direction<{t},",
+}
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("rve_kernels.h", "rve_device.h", "rve_solver.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2110_00733_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name, kind, tname):
+    """HBM bytes per launch of `kind` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or
+    None when there is none or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{workload_name}_pmc_traffic.md")
+    if not os.path.exists(path) or kind not in KIND_TO_KERNEL:
+        return None
+    txt = open(path).read()
+    if f"kernel sources hash: {kernel_sources_hash()}" not in txt:
+        return None
+    data = json.loads(txt.split("machine-readable (bytes per launch): ", 1)[1].strip().splitlines()[0])
+    pat = KIND_TO_KERNEL[kind].format(t=tname).replace(" ", "")
+    for name, b in data.items():
+        nm = name.replace(" ", "")
+        if "*" in pat:
+            head, tail = pat.split("*")
+            if nm.startswith(head) and nm.endswith(tail):
+                return b
+        elif nm.startswith(pat):
+            return b
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,11 +123,24 @@ def main():
     ap.add_argument("--workload", default="octet256_defects")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1)
+    ap.add_argument("--profile-steps", type=int, default=1)
     ap.add_argument("--inner-floor", type=float, default=None,
                     help="FP32-mixed: relative reduction at which an inner FP32 sweep stops (library default 1e-5)")
     ap.add_argument("--precision", choices=["fp32-mixed", "fp64"], default=None,
                     help="override the workload's precision (fp64 = the plain FP64 GPU MINRES)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(args.calibrate_copy // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build's solver runs on a single MI355X "
               "(see DESIGN.md for how the path would shard); run with --gpus 1", file=sys.stderr)
@@ -122,8 +175,6 @@ def main():
     for i in range(args.warmup):
         out = one()
         log(f"warmup {i}: status {out['status']} iters {out['iterations'].tolist()} res {out['rel_residual'].tolist()}")
-    rve.profile_reset()
-    rve.profile_enable(True)
     torch.cuda.synchronize()
     times, iters, res = [], [], []
     for i in range(args.steps):
@@ -136,11 +187,20 @@ def main():
         iters.append(int(out["iterations"].sum()))
         res.append(float(out["rel_residual"].max()))
         log(f"step {i}: {1e3 * (te - ts):.1f} ms, iters {out['iterations'].tolist()}, res {out['rel_residual'].tolist()}")
-    rve.profile_enable(False)
-    prof = rve.profile_read()
     total_t = sum(times)
     value = nvox * sum(iters) / total_t
     ms_per_step = 1e3 * total_t / args.steps
+    # per-kernel durations: the same solve with every launch bracketed by HIP events on the solve
+    # stream (profiled solves launch directly instead of replaying the captured graph)
+    rve.profile_reset()
+    rve.profile_enable(True)
+    tp = time.perf_counter()
+    for i in range(args.profile_steps):
+        out = one()
+    torch.cuda.synchronize()
+    log(f"profiled steps: {1e3 * (time.perf_counter() - tp) / max(args.profile_steps, 1):.1f} ms per solve")
+    rve.profile_enable(False)
+    prof = rve.profile_read()
 
     # roofline entry for the kernel with the largest share of the timed loop
     elem = 8 if prec == rve.FP64 else 4
@@ -157,8 +217,9 @@ def main():
     if dom:
         kd = kernels[dom]
         ach = kd["gbs"] or 0.0
+        traffic = measured_traffic(cfg["workload"], dom, "double" if prec == rve.FP64 else "float")
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "avg_us": round(kd["avg_us"], 2),
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "avg_us": round(kd["avg_us"], 2),
                 "alg_bytes_per_launch": kd["alg_bytes"]}
     log(json.dumps({k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()}))

@@ -20,7 +20,11 @@
  *   - the caller owns every buffer.  The library keeps no pointer after a call returns and never
  *     allocates device memory: all scratch comes from the caller's workspace.
  *   - calls run on the given HIP stream (NULL = default stream); host outputs are written and the
- *     stream is synchronised before the call returns.
+ *     stream is synchronised before the call returns.  solve_rve captures each chunk of check_every
+ *     MINRES iterations (rounded up to a multiple of 6) into a HIP graph that it replays until
+ *     convergence and keeps cached for the next call with the same buffers (capture needs a non-NULL
+ *     stream; with the NULL stream, or RVE_DISABLE_GRAPHS=1 in the environment, it launches directly).
+ *     Concurrent solve_rve calls in one process are serialised.
  *   - argument validation happens on the host before any HIP call; a rejected call touches no
  *     device state.
  */
@@ -126,11 +130,15 @@ rve_status rve_apply(const rve_grid* grid, const float* voxel_fraction_field, co
  * P3 FFT axis 0 + projection + inverse, P4 inverse FFT axis 1, P5 inverse FFT axis 2 + Lanczos
  * update, S1 Lanczos alpha, S2 Givens step, U2 direction + solution update.
  * rve_profile_read fills total milliseconds and launch counts for up to max_kinds kinds and
- * returns the number of kinds.  Not thread-safe with concurrent solves. */
+ * returns the number of kinds.  Profiled solves launch their kernels directly (no graph replay), so
+ * each launch can be bracketed; kernel durations do not depend on the launch path. */
 void rve_profile_enable(int32_t on);
 void rve_profile_reset(void);
 int32_t rve_profile_read(double* total_ms, int64_t* launches, int32_t max_kinds);
 const char* rve_profile_kind_name(int32_t kind);
+
+/* Text of the last HIP runtime failure behind an RVE_EDEVICE in this thread ("" if none). */
+const char* rve_last_error(void);
 
 /* Human-readable name of a status code (static string). */
 const char* rve_status_string(rve_status s);

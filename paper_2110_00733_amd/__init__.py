@@ -25,13 +25,16 @@ APPLY_OPERATOR, APPLY_PROJECTION, APPLY_STIFFNESS_ROUNDTRIP = 0, 1, 2
 # every symbol include/rve.h declares
 ABI_SYMBOLS = ("rve_default_options", "rve_supported_length", "rve_validate", "rve_workspace_bytes", "solve_rve",
                "rve_apply_workspace_bytes", "rve_apply", "rve_profile_enable", "rve_profile_reset", "rve_profile_read",
-               "rve_profile_kind_name", "rve_status_string")
+               "rve_profile_kind_name", "rve_last_error", "rve_status_string")
 
 
 class RveError(RuntimeError):
     def __init__(self, status: int, where: str = ""):
         self.status = status
-        super().__init__(f"{where}: {status_string(status)} ({status})")
+        extra = ""
+        if status == RVE_EDEVICE:
+            extra = ": " + load_library().rve_last_error().decode()
+        super().__init__(f"{where}: {status_string(status)} ({status}){extra}")
 
 
 class Grid(ctypes.Structure):
@@ -80,6 +83,8 @@ def load_library():
     lib.rve_profile_read.restype = ctypes.c_int32
     lib.rve_profile_kind_name.argtypes = [ctypes.c_int32]
     lib.rve_profile_kind_name.restype = ctypes.c_char_p
+    lib.rve_last_error.argtypes = []
+    lib.rve_last_error.restype = ctypes.c_char_p
     lib.rve_status_string.argtypes = [ctypes.c_int]
     lib.rve_status_string.restype = ctypes.c_char_p
     _lib = lib
@@ -167,6 +172,18 @@ def _stream_ptr(torch, device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+_solver_streams = {}
+
+
+def _solver_stream(torch, device):
+    """A dedicated (default-priority) stream per device: solve_rve captures its iteration chunks into
+    HIP graphs, which needs a non-NULL stream."""
+    key = torch.device(device).index
+    if key not in _solver_streams:
+        _solver_streams[key] = torch.cuda.Stream(device=device)
+    return _solver_streams[key]
+
+
 class Workspace:
     """Reusable device workspace (a torch uint8 buffer), grown on demand."""
 
@@ -215,12 +232,16 @@ def solve(phi, C_solid, macro_strain, *, C_void=None, L=(1.0, 1.0, 1.0), opt: Op
     eff = np.zeros((nc, 6))
     its = np.zeros(nc, dtype=np.int32)
     res = np.zeros(nc)
+    cur = torch.cuda.current_stream(phi.device)
+    ss = _solver_stream(torch, phi.device)
+    ss.wait_stream(cur)  # inputs written on the caller's stream are ready
     st = lib.solve_rve(ctypes.byref(g), ctypes.c_void_p(phi.data_ptr()), _dp(C), _dp(E), nc, ctypes.byref(opt),
                        ctypes.c_void_p(eps0.data_ptr()) if eps0 is not None else None,
                        ctypes.c_void_p(strain.data_ptr()),
                        ctypes.c_void_p(stress.data_ptr()) if stress is not None else None,
                        _dp(eff), its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(res),
-                       ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), _stream_ptr(torch, phi.device))
+                       ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), ctypes.c_void_p(ss.cuda_stream))
+    cur.wait_stream(ss)  # solve_rve returns after synchronising its stream; keep torch's ordering explicit
     if check and st < 0:
         raise RveError(st, "solve_rve")
     return dict(strain=strain, stress=stress, eff_stress=eff, iterations=its, rel_residual=res, status=int(st))

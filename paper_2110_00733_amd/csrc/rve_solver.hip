@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
@@ -61,6 +62,7 @@ static size_t next = 0;
 static double ms[NKIND];
 static long long cnt[NKIND];
 static long long dropped = 0;
+static size_t reserved = 0;  // pool slots owned by a captured graph
 static std::mutex mu;
 static inline void begin(int kind, hipStream_t s) {
   if (!on) return;
@@ -76,9 +78,9 @@ static inline void end(hipStream_t s) {
   if (!on || pending.empty() || (size_t)pending.back().second + 1 != next - 1) return;
   hipEventRecord(pool[pending.back().second + 1], s);
 }
-static void flush() {
+static void read_pairs(const std::vector<std::pair<int, int>>& pairs) {
   if (!on) return;
-  for (auto& pe : pending) {
+  for (auto& pe : pairs) {
     float t = 0.f;
     if (hipEventSynchronize(pool[pe.second + 1]) == hipSuccess &&
         hipEventElapsedTime(&t, pool[pe.second], pool[pe.second + 1]) == hipSuccess) {
@@ -86,8 +88,12 @@ static void flush() {
       cnt[pe.first] += 1;
     }
   }
+}
+static void flush() {
+  if (!on) return;
+  read_pairs(pending);
   pending.clear();
-  next = 0;
+  next = reserved;
 }
 }  // namespace prof
 
@@ -506,10 +512,19 @@ static Tables<T> tables_at(const Plan& pl, char* base) {
   return t;
 }
 
+// Text of the last HIP failure seen by this library (for diagnostics; see rve_last_error()).
+static thread_local char g_last_error[256] = "";
+static void note_hip_error(hipError_t e, const char* expr, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s (%d) in '%s' at rve_solver.hip:%d", hipGetErrorString(e), (int)e,
+           expr, line);
+}
 #define HIPCHK(x)                          \
   do {                                     \
     hipError_t e_ = (x);                   \
-    if (e_ != hipSuccess) return RVE_EDEVICE; \
+    if (e_ != hipSuccess) {                \
+      note_hip_error(e_, #x, __LINE__);    \
+      return RVE_EDEVICE;                  \
+    }                                      \
   } while (0)
 
 template <typename T>
@@ -642,40 +657,152 @@ struct ProfScope {
   ~ProfScope() { prof::on = saved; }
 };
 
+// Enqueue `count` MINRES iterations starting from buffer phase (ia, ib, ic, id1, id2); returns the
+// phase after them.  The buffer roles rotate with period 3 (u) and 2 (d).
+template <typename T>
+static void enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, const float* phi, const Material<T>& mat,
+                               const Tables<T>& tb, cx<T>* spec, MinresState* st, double* part, int count, int ph[5],
+                               hipStream_t s) {
+  const long long n6 = 6 * pl.g.nvox;
+  dim3 vg, vb;
+  vec_grid(nc, &vg, &vb);
+  // 16-byte access needs each case's field to start on a 16-byte boundary
+  const bool vec = (n6 * (long long)sizeof(T)) % 16 == 0;
+  int& ia = ph[0];
+  int& ib = ph[1];
+  int& ic = ph[2];
+  int& id1 = ph[3];
+  int& id2 = ph[4];
+  for (int j = 0; j < count; ++j) {
+    apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s);
+    prof::begin(prof::U2, s);
+    if (vec)
+      hipLaunchKernelGGL((k_direction<T, true>), vg, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
+    else
+      hipLaunchKernelGGL((k_direction<T, false>), vg, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
+    prof::end(s);
+    const int t0 = ia;
+    ia = ib;
+    ib = ic;
+    ic = t0;
+    std::swap(id1, id2);
+  }
+}
+
+// A captured chunk of MINRES iterations, replayed until every case has finished.  The key holds every
+// value baked into the captured launches; a solve with other pointers, sizes or material recaptures.
+struct ChunkGraph {
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::vector<unsigned char> key;
+  std::vector<std::pair<int, int>> prof_pairs;  // event pairs recorded inside the graph
+  void reset() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key.clear();
+    prof_pairs.clear();
+  }
+};
+static ChunkGraph g_chunk_graph[2];  // [0] FP32 fields, [1] FP64 fields
+
+template <typename T>
+static std::vector<unsigned char> chunk_key(const Plan& pl, int nc, const MinresBufs<T>& B, const float* phi,
+                                            const Material<T>& mat, const Tables<T>& tb, const cx<T>* spec,
+                                            const MinresState* st, const double* part, int chunk) {
+  std::vector<unsigned char> k;
+  auto put = [&](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    k.insert(k.end(), c, c + n);
+  };
+  put(pl.n, sizeof(pl.n));
+  put(&nc, sizeof(nc));
+  put(&B, sizeof(B));
+  put(&phi, sizeof(phi));
+  put(&mat, sizeof(mat));
+  put(&tb, sizeof(tb));
+  put(&spec, sizeof(spec));
+  put(&st, sizeof(st));
+  put(&part, sizeof(part));
+  put(&chunk, sizeof(chunk));
+  const bool po = prof::on;
+  put(&po, sizeof(po));
+  return k;
+}
+
+static bool graphs_enabled() {
+  const char* e = getenv("RVE_DISABLE_GRAPHS");
+  return !(e && e[0] == '1');
+}
+
+// Runs MINRES iterations until every case has finished or the iteration budget is spent.
+// States must be initialised (k_minres_init).  Host polls the finish flags every `check` iterations;
+// each chunk of `check` iterations (rounded up to the buffer-rotation period 6) is one hipGraph replay.
 template <typename T>
 static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const float* phi, const Material<T>& mat,
                               const Tables<T>& tb, cx<T>* spec, MinresState* st, double* part, int max_iter,
                               int check, hipStream_t s) {
-  const long long n6 = 6 * pl.g.nvox;
-  dim3 vg, vb;
-  vec_grid(nc, &vg, &vb);
   std::vector<MinresState> hs(nc);
   ProfScope prof_scope(true);
-  // 16-byte access needs each case's field to start on a 16-byte boundary
-  const bool vec = (n6 * (long long)sizeof(T)) % 16 == 0;
-  int ia = 0, ib = 1, ic = 2, id1 = 0, id2 = 1;  // u_{k-1}, u_k, p ; d_{k-1}, d_{k-2}
+  const int chunk = ((check + 5) / 6) * 6;
+  ChunkGraph& G = g_chunk_graph[sizeof(T) == 8 ? 1 : 0];
+  // per-kernel event timing brackets individual launches: profiled solves launch directly
+  bool use_graph = graphs_enabled() && !prof::on;
+  if (use_graph) {
+    std::vector<unsigned char> key = chunk_key<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk);
+    if (G.exec == nullptr || G.key != key) {
+      G.reset();
+      prof::flush();
+      prof::reserved = 0;  // the old graph's event slots are free again
+      prof::next = 0;
+      const size_t ev0 = prof::next;
+      int ph[5] = {0, 1, 2, 0, 1};
+      bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk, ph, s);
+        const hipError_t le = hipGetLastError();
+        hipGraph_t gr = nullptr;
+        ok = hipStreamEndCapture(s, &gr) == hipSuccess && le == hipSuccess && gr != nullptr;
+        if (ok) {
+          G.graph = gr;
+          ok = hipGraphInstantiate(&G.exec, gr, nullptr, nullptr, 0) == hipSuccess;
+        } else if (gr) {
+          hipGraphDestroy(gr);
+        }
+      }
+      if (ok) {
+        G.key = key;
+        G.prof_pairs = prof::pending;  // events recorded during capture belong to the graph
+        prof::pending.clear();
+        prof::reserved = prof::next;
+      } else {
+        G.reset();
+        (void)hipGetLastError();
+        prof::pending.clear();
+        prof::next = ev0;
+        use_graph = false;
+      }
+    }
+  }
+  int ph[5] = {0, 1, 2, 0, 1};  // u_{k-1}, u_k, p ; d_{k-1}, d_{k-2}
   int it = 0;
   while (it < max_iter) {
-    const int chunk = std::min(check, max_iter - it);
-    for (int j = 0; j < chunk; ++j) {
-      apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s);
-      prof::begin(prof::U2, s);
-      if (vec)
-        hipLaunchKernelGGL((k_direction<T, true>), vg, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
-      else
-        hipLaunchKernelGGL((k_direction<T, false>), vg, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
-      prof::end(s);
-      const int t0 = ia;
-      ia = ib;
-      ib = ic;
-      ic = t0;
-      std::swap(id1, id2);
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(G.exec, s));
+      it += chunk;
+    } else {
+      const int n = std::min(check, max_iter - it);
+      enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, n, ph, s);
+      it += n;
     }
-    it += chunk;
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(hs.data(), st, sizeof(MinresState) * nc, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    prof::flush();
+    if (use_graph)
+      prof::read_pairs(G.prof_pairs);
+    else
+      prof::flush();
     bool all = true;
     for (int c = 0; c < nc; ++c) all = all && hs[c].finish;
     if (all) break;
@@ -741,6 +868,8 @@ int32_t rve_profile_read(double* total_ms, int64_t* launches, int32_t max_kinds)
 }
 
 const char* rve_profile_kind_name(int32_t k) { return (k >= 0 && k < prof::NKIND) ? prof::kNames[k] : ""; }
+
+const char* rve_last_error(void) { return g_last_error; }
 
 const char* rve_status_string(rve_status s) {
   switch (s) {
@@ -880,10 +1009,13 @@ rve_status rve_apply(const rve_grid* grid, const float* phi, const double* phase
   return RVE_OK;
 }
 
+static std::mutex g_solve_mutex;  // solves share the captured-graph cache and the profiler
+
 rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase_stiffness,
                      const double* macro_strain, int32_t n_cases, const rve_options* opt, const void* eps0,
                      void* strain_out, void* stress_out, double* eff_stress, int32_t* iterations,
                      double* rel_residual, void* workspace, size_t workspace_bytes, void* hip_stream) {
+  std::lock_guard<std::mutex> solve_lock(g_solve_mutex);
   rve_status st = rve_validate(grid, phase_stiffness, macro_strain, n_cases, opt);
   if (st != RVE_OK) return st;
   if (!phi || !strain_out || !eff_stress || !iterations || !rel_residual || !workspace) return RVE_EINVAL;
