@@ -24,7 +24,7 @@
  *     MINRES iterations (rounded up to a multiple of 6) into a HIP graph that it replays until
  *     convergence and keeps cached for the next call with the same buffers (capture needs a non-NULL
  *     stream; with the NULL stream, or RVE_DISABLE_GRAPHS=1 in the environment, it launches directly).
- *     Concurrent solve_rve calls in one process are serialised.
+ *     The graph cache is per host thread; solves on different threads and streams may run concurrently.
  *   - argument validation happens on the host before any HIP call; a rejected call touches no
  *     device state.
  */
@@ -110,6 +110,35 @@ rve_status solve_rve(const rve_grid* grid, const float* voxel_fraction_field, co
                      void* strain_out, void* stress_out, double* eff_stress, int32_t* iterations,
                      double* rel_residual, void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* One RVE of a heterogeneous batch: the arguments of a solve_rve call (see there), plus its status. */
+typedef struct {
+  rve_grid grid;
+  const float* voxel_fraction_field; /* device [N] */
+  const double* phase_stiffness;     /* host [2][36] */
+  const double* macro_strain;        /* host [n_cases][6] */
+  int32_t n_cases;
+  const void* eps0;                  /* device [n_cases][6][N] or NULL */
+  void* strain_out;                  /* device [n_cases][6][N] */
+  void* stress_out;                  /* device [n_cases][6][N] or NULL */
+  double* eff_stress;                /* host [n_cases][6] */
+  int32_t* iterations;               /* host [n_cases] */
+  double* rel_residual;              /* host [n_cases] */
+  int32_t status;                    /* out: this RVE's solve_rve status */
+} rve_batch_item;
+
+/* Workspace for solve_rve_batch: min(n_streams, n_items) slots of the largest item's requirement. */
+size_t rve_batch_workspace_bytes(const rve_batch_item* items, int32_t n_items, const rve_options* opt,
+                                 int32_t n_streams);
+
+/* Many RVEs of uneven size (each with its own grid, phase map and load cases) solved concurrently:
+ * one host worker per stream (n_streams HIP streams, all on the current device, default priority)
+ * claims the largest remaining RVE, solves it on its stream with its own workspace slot, and replays
+ * its own captured iteration graph; kernels of different RVEs overlap on the GPU.  All items are
+ * validated before any work starts.  Returns the worst status; per-item statuses are in items[i].status.
+ * The per-kernel profiler (rve_profile_*) is shared by the workers. */
+rve_status solve_rve_batch(rve_batch_item* items, int32_t n_items, const rve_options* opt, void* workspace,
+                           size_t workspace_bytes, void* const* hip_streams, int32_t n_streams);
+
 /* Workspace bytes rve_apply needs. */
 size_t rve_apply_workspace_bytes(const rve_grid* grid, int32_t n_cases, int32_t precision);
 
@@ -136,6 +165,24 @@ void rve_profile_enable(int32_t on);
 void rve_profile_reset(void);
 int32_t rve_profile_read(double* total_ms, int64_t* launches, int32_t max_kinds);
 const char* rve_profile_kind_name(int32_t kind);
+
+/* Autotuner.  Times the operator apply for every admissible tile width of each pass kind (P3 pencils
+ * per block, P2/P4 rows per block, P1/P5 rows per block; coordinate descent, HIP events on
+ * hip_stream, 3 repetitions each) for this grid and precision, using the caller's workspace (at least
+ * rve_workspace_bytes(grid, n_cases, default options of that precision)).  The fastest tiles are kept
+ * in a process-wide table used by every later solve_rve / rve_apply on the same grid and precision,
+ * and, if cache_path is non-NULL, the whole table is written there (one JSON object per line).
+ * best_ms (host, may be NULL) receives the tuned apply time in milliseconds. */
+rve_status rve_autotune(const rve_grid* grid, int32_t n_cases, int32_t precision, void* workspace,
+                        size_t workspace_bytes, void* hip_stream, const char* cache_path, double* best_ms);
+
+/* Loads a table written by rve_autotune (also read once from $RVE_TUNE_FILE when the library first
+ * plans a grid).  Returns the number of entries loaded, -1 if the file cannot be read. */
+int32_t rve_load_tuning(const char* path);
+
+/* Tiles the next call on this grid and precision will use: tiles3 = {P1/P5 rows, P3 pencils,
+ * P2/P4 rows}.  Returns 1 if they come from the tuner, 0 if they are the built-in heuristic. */
+int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles3);
 
 /* Text of the last HIP runtime failure behind an RVE_EDEVICE in this thread ("" if none). */
 const char* rve_last_error(void);

@@ -25,7 +25,8 @@ APPLY_OPERATOR, APPLY_PROJECTION, APPLY_STIFFNESS_ROUNDTRIP = 0, 1, 2
 # every symbol include/rve.h declares
 ABI_SYMBOLS = ("rve_default_options", "rve_supported_length", "rve_validate", "rve_workspace_bytes", "solve_rve",
                "rve_apply_workspace_bytes", "rve_apply", "rve_profile_enable", "rve_profile_reset", "rve_profile_read",
-               "rve_profile_kind_name", "rve_last_error", "rve_status_string")
+               "rve_profile_kind_name", "rve_batch_workspace_bytes", "solve_rve_batch", "rve_autotune", "rve_load_tuning", "rve_tuned_tiles", "rve_last_error",
+               "rve_status_string")
 
 
 class RveError(RuntimeError):
@@ -45,6 +46,15 @@ class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("nyquist", ctypes.c_int32), ("scheme", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("inner_floor", ctypes.c_double), ("inner_safety", ctypes.c_double)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("voxel_fraction_field", ctypes.c_void_p),
+                ("phase_stiffness", ctypes.POINTER(ctypes.c_double)), ("macro_strain", ctypes.POINTER(ctypes.c_double)),
+                ("n_cases", ctypes.c_int32), ("eps0", ctypes.c_void_p), ("strain_out", ctypes.c_void_p),
+                ("stress_out", ctypes.c_void_p), ("eff_stress", ctypes.POINTER(ctypes.c_double)),
+                ("iterations", ctypes.POINTER(ctypes.c_int32)), ("rel_residual", ctypes.POINTER(ctypes.c_double)),
+                ("status", ctypes.c_int32)]
 
 
 _lib = None
@@ -83,6 +93,18 @@ def load_library():
     lib.rve_profile_read.restype = ctypes.c_int32
     lib.rve_profile_kind_name.argtypes = [ctypes.c_int32]
     lib.rve_profile_kind_name.restype = ctypes.c_char_p
+    bp = ctypes.POINTER(BatchItem)
+    lib.rve_batch_workspace_bytes.argtypes = [bp, ctypes.c_int32, op, ctypes.c_int32]
+    lib.rve_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.solve_rve_batch.argtypes = [bp, ctypes.c_int32, op, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p),
+                                    ctypes.c_int32]
+    lib.solve_rve_batch.restype = ctypes.c_int
+    lib.rve_autotune.argtypes = [gp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t, vp, ctypes.c_char_p, dp]
+    lib.rve_autotune.restype = ctypes.c_int
+    lib.rve_load_tuning.argtypes = [ctypes.c_char_p]
+    lib.rve_load_tuning.restype = ctypes.c_int32
+    lib.rve_tuned_tiles.argtypes = [gp, ctypes.c_int32, ip]
+    lib.rve_tuned_tiles.restype = ctypes.c_int32
     lib.rve_last_error.argtypes = []
     lib.rve_last_error.restype = ctypes.c_char_p
     lib.rve_status_string.argtypes = [ctypes.c_int]
@@ -106,6 +128,39 @@ def profile_read() -> dict:
     cnt = np.zeros(16, dtype=np.int64)
     k = lib.rve_profile_read(_dp(ms), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 16)
     return {lib.rve_profile_kind_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}
+
+
+def autotune(n, n_cases: int = 1, precision: int = FP32_MIXED, cache_path: str | None = None,
+             L=(1.0, 1.0, 1.0), device="cuda:0", workspace: Workspace | None = None) -> dict:
+    """rve_autotune for a grid: returns {"ms": tuned apply time, "tiles": (P1/P5 rows, P3 pencils, P2/P4 rows)}."""
+    torch = _torch()
+    lib = load_library()
+    g = make_grid(n, L)
+    opt = default_options(precision=precision)
+    nbytes = lib.rve_workspace_bytes(ctypes.byref(g), int(n_cases), ctypes.byref(opt))
+    if nbytes == 0:
+        raise RveError(RVE_EUNSUPPORTED_SIZE, "rve_workspace_bytes")
+    ws = (workspace or _default_ws).get(nbytes, torch.device(device))
+    ms = np.zeros(1)
+    ss = _solver_stream(torch, ws.device)
+    st = lib.rve_autotune(ctypes.byref(g), int(n_cases), int(precision), ctypes.c_void_p(ws.data_ptr()),
+                          ctypes.c_size_t(ws.numel()), ctypes.c_void_p(ss.cuda_stream),
+                          cache_path.encode() if cache_path else None, _dp(ms))
+    if st != RVE_OK:
+        raise RveError(st, "rve_autotune")
+    return {"ms": float(ms[0]), "tiles": tuned_tiles(n, precision, L)[0]}
+
+
+def tuned_tiles(n, precision: int = FP32_MIXED, L=(1.0, 1.0, 1.0)):
+    """((P1/P5 rows, P3 pencils, P2/P4 rows), from_tuner)"""
+    g = make_grid(n, L)
+    t = (ctypes.c_int32 * 3)()
+    f = load_library().rve_tuned_tiles(ctypes.byref(g), int(precision), t)
+    return tuple(t), bool(f)
+
+
+def load_tuning(path: str) -> int:
+    return int(load_library().rve_load_tuning(path.encode()))
 
 
 def status_string(s: int) -> str:
@@ -245,6 +300,66 @@ def solve(phi, C_solid, macro_strain, *, C_void=None, L=(1.0, 1.0, 1.0), opt: Op
     if check and st < 0:
         raise RveError(st, "solve_rve")
     return dict(strain=strain, stress=stress, eff_stress=eff, iterations=its, rel_residual=res, status=int(st))
+
+
+_batch_streams = []
+
+
+def solve_batch(rves, C_solid, *, C_void=None, n_streams: int = 8, opt: Options | None = None,
+                want_stress: bool = False, workspace: Workspace | None = None, check: bool = True, **opt_kw) -> dict:
+    """solve_rve_batch: `rves` is a list of (phi [n0,n1,n2] float32 CUDA tensor, macro strains [nc,6]),
+    grids may differ.  Returns dict(results=[per-RVE dict like solve()], status)."""
+    torch = _torch()
+    lib = load_library()
+    opt = opt or default_options(**opt_kw)
+    fdt = torch.float32 if opt.precision == FP32_MIXED else torch.float64
+    C = _stiffness(C_solid, C_void)
+    keep = [C]
+    items = (BatchItem * len(rves))()
+    results = []
+    dev = rves[0][0].device
+    for i, (phi, E) in enumerate(rves):
+        if not (phi.is_cuda and phi.dtype == torch.float32 and phi.dim() == 3 and phi.is_contiguous()):
+            raise ValueError("each phi must be a contiguous float32 CUDA tensor (n0, n1, n2)")
+        E = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(-1, 6))
+        n = tuple(phi.shape)
+        nc = E.shape[0]
+        r = dict(strain=torch.empty((nc, 6) + n, dtype=fdt, device=dev),
+                 stress=torch.empty((nc, 6) + n, dtype=fdt, device=dev) if want_stress else None,
+                 eff_stress=np.zeros((nc, 6)), iterations=np.zeros(nc, dtype=np.int32), rel_residual=np.zeros(nc))
+        results.append(r)
+        keep.append(E)
+        it = items[i]
+        it.grid = make_grid(n)
+        it.voxel_fraction_field = phi.data_ptr()
+        it.phase_stiffness = _dp(C)
+        it.macro_strain = _dp(E)
+        it.n_cases = nc
+        it.eps0 = None
+        it.strain_out = r["strain"].data_ptr()
+        it.stress_out = r["stress"].data_ptr() if want_stress else None
+        it.eff_stress = _dp(r["eff_stress"])
+        it.iterations = r["iterations"].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        it.rel_residual = _dp(r["rel_residual"])
+    while len(_batch_streams) < n_streams:
+        _batch_streams.append(torch.cuda.Stream(device=dev))
+    streams = (ctypes.c_void_p * n_streams)(*[s.cuda_stream for s in _batch_streams[:n_streams]])
+    nbytes = lib.rve_batch_workspace_bytes(items, len(rves), ctypes.byref(opt), n_streams)
+    if nbytes == 0:
+        raise RveError(RVE_EINVAL, "rve_batch_workspace_bytes")
+    ws = (workspace or _default_ws).get(nbytes, dev)
+    cur = torch.cuda.current_stream(dev)
+    for s_ in _batch_streams[:n_streams]:
+        s_.wait_stream(cur)
+    st = lib.solve_rve_batch(items, len(rves), ctypes.byref(opt), ctypes.c_void_p(ws.data_ptr()),
+                             ctypes.c_size_t(ws.numel()), streams, n_streams)
+    for s_ in _batch_streams[:n_streams]:
+        cur.wait_stream(s_)
+    for i, r in enumerate(results):
+        r["status"] = int(items[i].status)
+    if check and st < 0:
+        raise RveError(st, "solve_rve_batch")
+    return dict(results=results, status=int(st))
 
 
 def apply(x, phi=None, C_solid=None, *, C_void=None, mode: int = APPLY_OPERATOR, L=(1.0, 1.0, 1.0),

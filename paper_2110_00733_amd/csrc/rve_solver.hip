@@ -16,7 +16,9 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/rve.h"
@@ -38,12 +40,15 @@ const LenEntry* find_len(int n) {
 void register_group_a();
 void register_group_b();
 void register_group_c();
+extern "C" int32_t rve_load_tuning(const char* path);
 static void ensure_registry() {
   static std::once_flag once;
   std::call_once(once, [] {
     register_group_a();
     register_group_b();
     register_group_c();
+    const char* f = getenv("RVE_TUNE_FILE");
+    if (f && f[0]) rve_load_tuning(f);
   });
 }
 
@@ -66,6 +71,7 @@ static size_t reserved = 0;  // pool slots owned by a captured graph
 static std::mutex mu;
 static inline void begin(int kind, hipStream_t s) {
   if (!on) return;
+  std::lock_guard<std::mutex> lk(mu);
   if (next + 2 > pool.size()) {
     dropped++;
     return;
@@ -75,7 +81,9 @@ static inline void begin(int kind, hipStream_t s) {
   next += 2;
 }
 static inline void end(hipStream_t s) {
-  if (!on || pending.empty() || (size_t)pending.back().second + 1 != next - 1) return;
+  if (!on) return;
+  std::lock_guard<std::mutex> lk(mu);
+  if (pending.empty() || (size_t)pending.back().second + 1 != next - 1) return;
   hipEventRecord(pool[pending.back().second + 1], s);
 }
 static void read_pairs(const std::vector<std::pair<int, int>>& pairs) {
@@ -91,6 +99,7 @@ static void read_pairs(const std::vector<std::pair<int, int>>& pairs) {
 }
 static void flush() {
   if (!on) return;
+  std::lock_guard<std::mutex> lk(mu);
   read_pairs(pending);
   pending.clear();
   next = reserved;
@@ -378,12 +387,44 @@ __global__ void k_check_phi(const float* phi, long long n, int* bad) {
 // ============================================================================ plan + workspace
 static long long align_up(long long v, long long a) { return (v + a - 1) / a * a; }
 
+struct Tiles {
+  int W1, W3, R2;  // P1/P5 row tile, P3 pencil tile, P2/P4 rows per block
+};
 struct Plan {
   int n[3];
   GridDims g;
   const LenEntry* ax[3];
-  int W1, W3, R2;  // P1/P5 row tile, P3 pencil tile, P2/P4 rows per block
+  Tiles t[2];  // [0] FP32 kernels, [1] FP64 kernels
 };
+
+// Tuned tiles per (grid, precision), filled by rve_autotune / rve_load_tuning.
+struct TuneKey {
+  int n0, n1, n2, elem;
+  bool operator==(const TuneKey& o) const { return n0 == o.n0 && n1 == o.n1 && n2 == o.n2 && elem == o.elem; }
+};
+static std::vector<std::pair<TuneKey, Tiles>>& tuned() {
+  static std::vector<std::pair<TuneKey, Tiles>> t;
+  return t;
+}
+static std::mutex g_tune_mutex;
+static bool find_tuned(const TuneKey& k, Tiles* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mutex);
+  for (auto& e : tuned())
+    if (e.first == k) {
+      *out = e.second;
+      return true;
+    }
+  return false;
+}
+static void set_tuned(const TuneKey& k, const Tiles& t) {
+  std::lock_guard<std::mutex> lk(g_tune_mutex);
+  for (auto& e : tuned())
+    if (e.first == k) {
+      e.second = t;
+      return;
+    }
+  tuned().push_back({k, t});
+}
 
 static int pick_tile(int threads_per_row, int len) {
   int W = std::max(1, std::min(64, 256 / threads_per_row));
@@ -395,19 +436,19 @@ static int pick_tile(int threads_per_row, int len) {
 constexpr long long kLdsCap = 64 * 1024;
 static int tile_p1(const Plan& pl, int elem) {
   const int na = pl.ax[2]->na, nb = pl.ax[2]->nb;
-  int W = pl.W1;
+  int W = pl.t[elem == 8].W1;
   while (W > 1 && 2LL * elem * W * std::max(na * (nb + 1), pl.g.n2 + 1) > kLdsCap) W /= 2;
   return W;
 }
 static int tile_p3(const Plan& pl, int elem) {
   const int na = pl.ax[0]->na, nb = pl.ax[0]->nb;
-  int W = pl.W3;
+  int W = pl.t[elem == 8].W3;
   while (W > 1 && 2LL * elem * na * (nb * W + 1) > kLdsCap) W /= 2;
   return W;
 }
 static int rows_p2(const Plan& pl, int elem) {
   const int na = pl.ax[1]->na, nb = pl.ax[1]->nb;
-  int R = pl.R2;
+  int R = pl.t[elem == 8].R2;
   while (R > 1 && 2LL * elem * R * na * (nb + 1) > kLdsCap) R /= 2;
   return R;
 }
@@ -430,9 +471,14 @@ static bool make_plan(const rve_grid* grid, Plan* pl) {
   g.k2 = g.n2 / 2 + 1;
   g.nvox = (long long)g.n0 * g.n1 * g.n2;
   g.spec_case = 6LL * g.k2 * g.n0 * g.n1;
-  pl->W1 = pick_tile(pl->ax[2]->nb, g.n1);
-  pl->W3 = pick_tile(pl->ax[0]->nb, g.n1);
-  pl->R2 = std::max(1, std::min(64, 256 / pl->ax[1]->nb));
+  for (int e = 0; e < 2; ++e) {
+    Tiles& t = pl->t[e];
+    t.W1 = pick_tile(pl->ax[2]->nb, g.n1);
+    t.W3 = pick_tile(pl->ax[0]->nb, g.n1);
+    t.R2 = std::max(1, std::min(64, 256 / pl->ax[1]->nb));
+    Tiles tt;
+    if (find_tuned(TuneKey{g.n0, g.n1, g.n2, e ? 8 : 4}, &tt)) t = tt;
+  }
   return true;
 }
 
@@ -461,7 +507,7 @@ static Layout make_layout(const Plan& pl, int nc, int precision, bool solve) {
   memset(&L, 0, sizeof(L));
   const GridDims& g = pl.g;
   const long long n6 = 6 * g.nvox * nc;
-  L.np_p5 = std::max(partials_p5(pl, 4), partials_p5(pl, 8));
+  L.np_p5 = g.n0 * g.n1;  // P1/P5 blocks at the narrowest possible tile (W = 1): any tuned tile fits
   L.np_vec = kRedBlocks;
   L.np_post = 6 * kRedBlocks;
   const int np_max = std::max(std::max(L.np_p5, L.np_vec), L.np_post);
@@ -705,7 +751,8 @@ struct ChunkGraph {
     prof_pairs.clear();
   }
 };
-static ChunkGraph g_chunk_graph[2];  // [0] FP32 fields, [1] FP64 fields
+// one cache per host thread: batch workers drive their own streams concurrently
+static thread_local ChunkGraph g_chunk_graph[2];  // [0] FP32 fields, [1] FP64 fields
 
 template <typename T>
 static std::vector<unsigned char> chunk_key(const Plan& pl, int nc, const MinresBufs<T>& B, const float* phi,
@@ -815,7 +862,11 @@ static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const fl
 using namespace rve;
 
 // ============================================================================ C ABI
+static std::mutex g_solve_mutex;  // serialises autotuning
+
 extern "C" {
+
+static rve_status validate_grid(const rve_grid* grid);
 
 void rve_default_options(rve_options* o) {
   if (!o) return;
@@ -870,6 +921,154 @@ int32_t rve_profile_read(double* total_ms, int64_t* launches, int32_t max_kinds)
 const char* rve_profile_kind_name(int32_t k) { return (k >= 0 && k < prof::NKIND) ? prof::kNames[k] : ""; }
 
 const char* rve_last_error(void) { return g_last_error; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- autotuner
+static bool tile_fits(int threads_per_row, int W) { return W >= 1 && W * threads_per_row <= 256; }
+
+static int write_tuning_file(const char* path) {
+  // one JSON object per line: {"n":[a,b,c],"elem":e,"W1":w,"W3":w,"R2":r}
+  std::lock_guard<std::mutex> lk(g_tune_mutex);
+  FILE* f = fopen(path, "w");
+  if (!f) return -1;
+  for (auto& e : tuned())
+    fprintf(f, "{\"n\":[%d,%d,%d],\"elem\":%d,\"W1\":%d,\"W3\":%d,\"R2\":%d}\n", e.first.n0, e.first.n1,
+            e.first.n2, e.first.elem, e.second.W1, e.second.W3, e.second.R2);
+  fclose(f);
+  return (int)tuned().size();
+}
+
+extern "C" int32_t rve_load_tuning(const char* path) {
+  if (!path) return -1;
+  FILE* f = fopen(path, "r");
+  if (!f) return -1;
+  char line[512];
+  int n = 0;
+  while (fgets(line, sizeof(line), f)) {
+    TuneKey k;
+    Tiles t;
+    if (sscanf(line, " {\"n\":[%d,%d,%d],\"elem\":%d,\"W1\":%d,\"W3\":%d,\"R2\":%d}", &k.n0, &k.n1, &k.n2,
+               &k.elem, &t.W1, &t.W3, &t.R2) == 7 &&
+        (k.elem == 4 || k.elem == 8) && t.W1 >= 1 && t.W3 >= 1 && t.R2 >= 1 && t.W1 <= 256 && t.W3 <= 256 &&
+        t.R2 <= 256) {
+      set_tuned(k, t);
+      n++;
+    }
+  }
+  fclose(f);
+  return n;
+}
+
+template <typename T>
+static rve_status autotune_impl(Plan& pl, const rve_grid* grid, int nc, const Layout& L, char* ws, hipStream_t s,
+                                Tiles* best, double* best_ms) {
+  const int elem = (int)sizeof(T);
+  const long long n6 = 6 * pl.g.nvox;
+  char* tab = ws + (elem == 4 ? L.off_tab32 : L.off_tab64);
+  rve_status r = build_tables<T>(pl, grid, tab, RVE_SCHEME_ROTATED, RVE_NYQ_NATURAL, s);
+  if (r != RVE_OK) return r;
+  Tables<T> tb = tables_at<T>(pl, tab);
+  T* x = reinterpret_cast<T*>(ws + (elem == 4 ? L.off_u32[0] : L.off_x64));
+  T* y = reinterpret_cast<T*>(ws + (elem == 4 ? L.off_u32[1] : L.off_r64));
+  cx<T>* spec = reinterpret_cast<cx<T>*>(ws + (elem == 4 ? L.off_spec32 : L.off_spec64));
+  hipLaunchKernelGGL(k_zero<T>, dim3(1024), dim3(256), 0, s, x, n6 * nc);
+  Material<T> id;
+  memset(&id, 0, sizeof(id));
+  for (int i = 0; i < 6; ++i) id.C0[i * 7] = (T)1;
+  id.has_c0 = 1;
+  id.use_phi = 0;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int reps = 3;
+  auto time_apply = [&](double* ms) -> rve_status {
+    apply_op<T>(pl, nc, x, nullptr, nullptr, id, tb, spec, y, nullptr, nullptr, nullptr, nullptr, 0, s);
+    HIPCHK(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i)
+      apply_op<T>(pl, nc, x, nullptr, nullptr, id, tb, spec, y, nullptr, nullptr, nullptr, nullptr, 0, s);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipGetLastError());
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    *ms = t / reps;
+    return RVE_OK;
+  };
+  Tiles& cur = pl.t[elem == 8];
+  double bms = 0;
+  r = time_apply(&bms);
+  if (r != RVE_OK) return r;
+  const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
+  // coordinate descent over the three tiles (P3 pencils, P2/P4 rows, P1/P5 rows)
+  for (int role = 0; role < 3; ++role) {
+    const int nb = role == 0 ? pl.ax[0]->nb : role == 1 ? pl.ax[1]->nb : pl.ax[2]->nb;
+    int* slot = role == 0 ? &cur.W3 : role == 1 ? &cur.R2 : &cur.W1;
+    const int keep = *slot;
+    int bestv = keep;
+    for (int c : cands) {
+      if (c == keep || !tile_fits(nb, c)) continue;
+      *slot = c;
+      // the LDS cap may reduce the candidate; skip duplicates of what it resolves to
+      const int eff = role == 0 ? tile_p3(pl, elem) : role == 1 ? rows_p2(pl, elem) : tile_p1(pl, elem);
+      if (eff != c) continue;
+      double ms = 0;
+      r = time_apply(&ms);
+      if (r != RVE_OK) {
+        *slot = keep;
+        return r;
+      }
+      if (ms < bms) {
+        bms = ms;
+        bestv = c;
+      }
+    }
+    *slot = bestv;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *best = cur;
+  if (best_ms) *best_ms = bms;
+  return RVE_OK;
+}
+
+extern "C" {
+
+rve_status rve_autotune(const rve_grid* grid, int32_t n_cases, int32_t precision, void* workspace,
+                        size_t workspace_bytes, void* hip_stream, const char* cache_path, double* best_ms) {
+  std::lock_guard<std::mutex> solve_lock(g_solve_mutex);
+  rve_status st = validate_grid(grid);
+  if (st != RVE_OK) return st;
+  if (n_cases < 1 || n_cases > 65535 || (precision != RVE_FP32_MIXED && precision != RVE_FP64) || !workspace)
+    return RVE_EINVAL;
+  Plan pl;
+  if (!make_plan(grid, &pl)) return RVE_EUNSUPPORTED_SIZE;
+  const Layout L = make_layout(pl, n_cases, precision, true);
+  if ((long long)workspace_bytes < L.total) return RVE_ENOMEM;
+  hipStream_t s = (hipStream_t)hip_stream;
+  Tiles best;
+  double ms = 0;
+  const int elem = precision == RVE_FP64 ? 8 : 4;
+  st = elem == 4 ? autotune_impl<float>(pl, grid, n_cases, L, (char*)workspace, s, &best, &ms)
+                 : autotune_impl<double>(pl, grid, n_cases, L, (char*)workspace, s, &best, &ms);
+  if (st != RVE_OK) return st;
+  set_tuned(TuneKey{pl.g.n0, pl.g.n1, pl.g.n2, elem}, best);
+  if (best_ms) *best_ms = ms;
+  if (cache_path && write_tuning_file(cache_path) < 0) return RVE_EINVAL;
+  return RVE_OK;
+}
+
+int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles3) {
+  if (validate_grid(grid) != RVE_OK || !tiles3) return 0;
+  Plan pl;
+  if (!make_plan(grid, &pl)) return 0;
+  const Tiles& t = pl.t[precision == RVE_FP64];
+  tiles3[0] = t.W1;
+  tiles3[1] = t.W3;
+  tiles3[2] = t.R2;
+  Tiles tt;
+  return find_tuned(TuneKey{pl.g.n0, pl.g.n1, pl.g.n2, precision == RVE_FP64 ? 8 : 4}, &tt) ? 1 : 0;
+}
 
 const char* rve_status_string(rve_status s) {
   switch (s) {
@@ -1009,13 +1208,10 @@ rve_status rve_apply(const rve_grid* grid, const float* phi, const double* phase
   return RVE_OK;
 }
 
-static std::mutex g_solve_mutex;  // solves share the captured-graph cache and the profiler
-
 rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase_stiffness,
                      const double* macro_strain, int32_t n_cases, const rve_options* opt, const void* eps0,
                      void* strain_out, void* stress_out, double* eff_stress, int32_t* iterations,
                      double* rel_residual, void* workspace, size_t workspace_bytes, void* hip_stream) {
-  std::lock_guard<std::mutex> solve_lock(g_solve_mutex);
   rve_status st = rve_validate(grid, phase_stiffness, macro_strain, n_cases, opt);
   if (st != RVE_OK) return st;
   if (!phi || !strain_out || !eff_stress || !iterations || !rel_residual || !workspace) return RVE_EINVAL;
@@ -1229,6 +1425,70 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
   }
   rve_status worst = worst_err != RVE_OK ? worst_err : worst_warn;
   return worst;
+}
+
+// ---------------------------------------------------------------------------- heterogeneous batches
+size_t rve_batch_workspace_bytes(const rve_batch_item* items, int32_t n_items, const rve_options* opt,
+                                 int32_t n_streams) {
+  if (!items || n_items < 1 || n_streams < 1 || !opt) return 0;
+  size_t mx = 0;
+  for (int i = 0; i < n_items; ++i) {
+    const size_t b = rve_workspace_bytes(&items[i].grid, items[i].n_cases, opt);
+    if (b == 0) return 0;
+    mx = std::max(mx, b);
+  }
+  const size_t slot = (mx + 255) / 256 * 256;
+  return slot * (size_t)std::min(n_streams, n_items);
+}
+
+rve_status solve_rve_batch(rve_batch_item* items, int32_t n_items, const rve_options* opt, void* workspace,
+                           size_t workspace_bytes, void* const* hip_streams, int32_t n_streams) {
+  if (!items || n_items < 1 || !opt || !workspace || !hip_streams || n_streams < 1) return RVE_EINVAL;
+  for (int i = 0; i < n_items; ++i) {
+    rve_status v = rve_validate(&items[i].grid, items[i].phase_stiffness, items[i].macro_strain, items[i].n_cases, opt);
+    if (v != RVE_OK) return v;
+    if (!items[i].voxel_fraction_field || !items[i].strain_out || !items[i].eff_stress || !items[i].iterations ||
+        !items[i].rel_residual)
+      return RVE_EINVAL;
+  }
+  const int workers = std::min(n_streams, n_items);
+  const size_t need = rve_batch_workspace_bytes(items, n_items, opt, workers);
+  if (need == 0) return RVE_EINVAL;
+  if (workspace_bytes < need) return RVE_ENOMEM;
+  const size_t slot = need / workers;
+  // largest work first (voxels x load cases), claimed dynamically by the stream workers
+  std::vector<int> order(n_items);
+  for (int i = 0; i < n_items; ++i) order[i] = i;
+  auto work = [&](int i) {
+    return (double)items[i].grid.n[0] * items[i].grid.n[1] * items[i].grid.n[2] * items[i].n_cases;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  std::atomic<int> next{0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RVE_EDEVICE;
+  auto worker = [&](int w) {
+    if (hipSetDevice(dev) != hipSuccess) return;
+    char* ws = (char*)workspace + slot * w;
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= n_items) break;
+      rve_batch_item& it = items[order[k]];
+      it.status = solve_rve(&it.grid, it.voxel_fraction_field, it.phase_stiffness, it.macro_strain, it.n_cases, opt,
+                            it.eps0, it.strain_out, it.stress_out, it.eff_stress, it.iterations, it.rel_residual,
+                            ws, slot, hip_streams[w]);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < workers; ++w) th.emplace_back(worker, w);
+  worker(0);
+  for (auto& t : th) t.join();
+  rve_status worst_err = RVE_OK, worst_warn = RVE_OK;
+  for (int i = 0; i < n_items; ++i) {
+    const rve_status s = (rve_status)items[i].status;
+    if (s < 0 && worst_err == RVE_OK) worst_err = s;
+    if (s > 0 && worst_warn == RVE_OK) worst_warn = s;
+  }
+  return worst_err != RVE_OK ? worst_err : worst_warn;
 }
 
 }  // extern "C"

@@ -309,3 +309,37 @@ def test_benchmark_workload_solution_properties():
     hm = float((sig.double() * eps.double()).sum(dim=1).mean())
     work = float(E[0] @ out["eff_stress"][0])
     assert abs(hm) < 1e-4 * work
+
+
+def test_autotune_then_solve_matches():
+    """Tuned tiles change only the grouping of reductions: same iterations (+-1), same <sigma>."""
+    rve = _rve()
+    n = (24, 48, 32)
+    phi, _ = li.octet_phase_map(n, 0.12)
+    d = _dev(phi)
+    E = np.eye(6)[[0, 3]]
+    ref = rve.solve(d, C1, E, tol=1e-8)
+    for prec in (rve.FP32_MIXED, rve.FP64):
+        res = rve.autotune(n, n_cases=2, precision=prec)
+        assert res["ms"] > 0
+        assert rve.tuned_tiles(n, prec)[1]
+    out = rve.solve(d, C1, E, tol=1e-8)
+    assert np.all(np.abs(out["iterations"] - ref["iterations"]) <= 1)
+    assert _rel(out["eff_stress"], ref["eff_stress"]) < 1e-7
+
+
+def test_heterogeneous_batch_matches_individual_solves():
+    """RVEs of uneven size on several streams give the single-RVE results."""
+    rve = _rve()
+    rves = []
+    for i, (n, rho) in enumerate(li.heterogeneous_rves(6, sizes=(16, 24, 32))):
+        phi, _ = li.octet_phase_map(n, rho)
+        rves.append((_dev(phi), np.eye(6)[[0, 3, 5]] if i % 2 else np.eye(6)[[1]]))
+    out = rve.solve_batch(rves, C1, n_streams=3, tol=1e-7)
+    assert out["status"] == 0
+    for (d, E), r in zip(rves, out["results"]):
+        single = rve.solve(d, C1, E, tol=1e-7)
+        assert r["status"] == 0
+        assert np.array_equal(r["iterations"], single["iterations"])
+        assert np.array_equal(r["eff_stress"], single["eff_stress"])
+        assert torch.equal(r["strain"], single["strain"])
