@@ -137,6 +137,8 @@ def main():
                     help="FP32-mixed: relative reduction at which an inner FP32 sweep stops (library default 1e-5)")
     ap.add_argument("--precision", choices=["fp32-mixed", "fp64"], default=None,
                     help="override the workload's precision (fp64 = the plain FP64 GPU MINRES)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the wall-time comparison plain FP64 / FP32-mixed / learned warm start")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (counter calibration) and exit")
     args = ap.parse_args()
@@ -244,6 +246,10 @@ def main():
     log(json.dumps({k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()}))
 
+    learned = None
+    if not args.no_learned and cfg["workload"] == "octet256_defects" and prec == rve.FP32_MIXED:
+        learned = learned_vs_plain(d, C1, E, cfg["tol"], ws, 1e-3 * ms_per_step, iters[-1])
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -262,8 +268,55 @@ def main():
             "value": value, "unit": "voxel-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64" if prec == rve.FP64 else "f32", "data": "synthetic", "config": cfg,
-            "roofline": roof, "cpu_baseline": cpu, "kernels": kernels}
+            "roofline": roof, "cpu_baseline": cpu, "learned_vs_plain": learned, "kernels": kernels}
     print(json.dumps(line), flush=True)
+
+
+def learned_vs_plain(d, C1, E, tol, ws, fp32_s, fp32_iters, repeats=2):
+    """Wall time to the tolerance for the plain FP64 GPU MINRES (zero start), the FP32-mixed solver
+    (zero start, the timed steps) and the FP32-mixed solver started from the trained network's
+    prediction (network inference, prolongation and projection included)."""
+    import torch
+    import paper_2110_00733_amd as rve
+    from paper_2110_00733_amd.nn import WarmStartNet
+    from paper_2110_00733_amd.warmstart_train import DEFAULT_WEIGHTS
+
+    def timed(fn):
+        best, out = None, None
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            best = dt if best is None else min(best, dt)
+        return best, out
+
+    t64, o64 = timed(lambda: rve.solve(d, C1, E, tol=tol, precision=rve.FP64, workspace=ws, want_stress=True))
+    res = {"plain_fp64_s": round(t64, 4), "plain_fp64_iterations": int(o64["iterations"].sum()),
+           "fp32_mixed_s": round(fp32_s, 4), "fp32_mixed_iterations": int(fp32_iters)}
+    if not os.path.exists(DEFAULT_WEIGHTS):
+        res["learned"] = None
+        return res
+    net = WarmStartNet().load(DEFAULT_WEIGHTS)
+    tl, ol = timed(lambda: rve.solve(d, C1, E, tol=tol, workspace=ws, want_stress=True, eps0=net.predict(d, E, grid=64)))
+    info = rve.last_solve_info()
+    torch.cuda.synchronize()
+    ti = time.perf_counter()
+    net.predict(d, E, grid=64)
+    torch.cuda.synchronize()
+    res.update({"learned_fp32_mixed_s": round(tl, 4), "learned_iterations": int(ol["iterations"].sum()),
+                "learned_inference_s": round(time.perf_counter() - ti, 4),
+                "learned_initial_rel_residual": float(info["initial_rel_residual"][0]),
+                "learned_start_rejected": bool(info["warm_rejected"][0]),
+                "eff_stress_rel_diff_learned_vs_fp64": float(np.max(np.abs(ol["eff_stress"] - o64["eff_stress"])) /
+                                                             np.max(np.abs(o64["eff_stress"]))),
+                "speedup_fp32_mixed_vs_plain_fp64": round(t64 / fp32_s, 3),
+                "speedup_learned_vs_plain_fp64": round(t64 / tl, 3),
+                "speedup_learned_vs_fp32_mixed": round(fp32_s / tl, 3),
+                "weights": os.path.relpath(DEFAULT_WEIGHTS, ROOT)})
+    log("learned vs plain: " + json.dumps(res))
+    return res
 
 
 def bench_batch(args, grids, phis, E, cfg, C1):

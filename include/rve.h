@@ -97,7 +97,9 @@ size_t rve_workspace_bytes(const rve_grid* grid, int32_t n_cases, const rve_opti
  *                         all zero) and of the solid ([1]); each must be symmetric and finite
  *   macro_strain          host double [n_cases][6]: Mandel macro strains Ebar
  *   eps0                  device [n_cases][6][N] warm start (float for FP32_MIXED, double for FP64) or
- *                         NULL for the zero start; it is projected onto compatible fields first
+ *                         NULL for the zero start; it is projected onto compatible fields first,
+ *                         and a case whose projected start has ||b - A x0|| >= ||b|| starts from
+ *                         zero instead (see rve_last_solve_info)
  *   strain_out            device [n_cases][6][N] (float / double): the fluctuation eps (total = Ebar+eps)
  *   stress_out            device [n_cases][6][N] (float / double) or NULL: sigma = C(x)(Ebar + eps)
  *   eff_stress            host double [n_cases][6]: volume average <sigma> (FP64); for unit Mandel
@@ -186,6 +188,13 @@ int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles3
 
 /* Text of the last HIP runtime failure behind an RVE_EDEVICE in this thread ("" if none). */
 const char* rve_last_error(void);
+
+/* Start of the last solve_rve that returned on this thread, per load case (first max_cases):
+ * initial_rel_residual[c] = ||b - A x0|| / ||b|| of the start x0 (0 for a zero right-hand side; 1 for
+ * a zero start), warm_rejected[c] = 1 if a warm start eps0 was dropped because that ratio was not
+ * below 1 (the solve then started from zero).  Either pointer may be NULL.  Returns the number of
+ * cases of that solve (0 if none). */
+int32_t rve_last_solve_info(double* initial_rel_residual, int32_t* warm_rejected, int32_t max_cases);
 
 /* Human-readable name of a status code (static string). */
 const char* rve_status_string(rve_status s);

@@ -136,16 +136,18 @@ class DefectInfo:
 
 def octet_defect_phase_map(n, rho: float = 0.15, rough_amp: float = 1.5, rough_sigma: float = 2.0,
                            n_pores: int = 200, pore_median_vox: float = 2.0, pore_s: float = 0.5,
-                           seed_rough: int = 20211001, seed_pores: int = 20211002, sub: int = 4):
+                           seed_rough: int = 20211001, seed_pores: int = 20211002, sub: int = 4,
+                           radius: float | None = None):
     """Octet with synthetic manufacturing defects.
 
     The radius is chosen for `rho` on the ideal geometry; the strut signed distance is then perturbed
     by rough_amp-voxel roughness (Gaussian-filtered U(-1,1) noise, std rough_sigma voxels), and
     `n_pores` spherical pores with lognormal radii (median pore_median_vox voxels, log-std pore_s)
     are carved from the solid (centres drawn until n_pores land inside the perturbed solid).
+    A given `radius` (unit cell = 1) replaces the density search (rho is then only recorded).
     """
     n, c = _n3(n)
-    r = octet_radius(n, rho, sub)
+    r = float(radius) if radius is not None else octet_radius(n, rho, sub)
     h = 1.0 / n[0]
     eta = roughness_field(n, rough_sigma, rough_amp, seed_rough) if rough_amp > 0 else None
     pores = np.zeros((max(n_pores, 1), 4), dtype=np.float64)

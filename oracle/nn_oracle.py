@@ -175,12 +175,18 @@ def backward(params, cache, dout):
     return grads
 
 
-def weighted_loss(pred, target, phi, void_weight, inv_norm, n_target=N_TARGET):
-    """L = inv_norm * sum_v sum_{c < n_target} (void_weight + phi[v]) (pred[v][c] - target[v][c])^2.
+def loss_weight(phi, weight3):
+    """w(v) = weight3[0] + weight3[1] phi[v] + weight3[2] (1 if 0 < phi[v] < 1 else 0)."""
+    a, b, c = weight3
+    return a + b * phi + c * ((phi > 0) & (phi < 1))
+
+
+def weighted_loss(pred, target, phi, weight3, inv_norm, n_target=N_TARGET):
+    """L = inv_norm * sum_v sum_{c < n_target} w(v) (pred[v][c] - target[v][c])^2, w = loss_weight(phi, weight3).
 
     pred [B,n,n,n,48], target [B,n,n,n,n_target] (channels-last here), phi [B,n,n,n].
     Returns (L, dL/dpred)."""
-    w = (void_weight + phi)[..., None]
+    w = loss_weight(phi, weight3)[..., None]
     d = pred[..., :n_target] - target
     L = inv_norm * float(np.sum(w * d * d))
     g = np.zeros_like(pred, dtype=np.float64)

@@ -26,7 +26,7 @@ APPLY_OPERATOR, APPLY_PROJECTION, APPLY_STIFFNESS_ROUNDTRIP = 0, 1, 2
 ABI_SYMBOLS = ("rve_default_options", "rve_supported_length", "rve_validate", "rve_workspace_bytes", "solve_rve",
                "rve_apply_workspace_bytes", "rve_apply", "rve_profile_enable", "rve_profile_reset", "rve_profile_read",
                "rve_profile_kind_name", "rve_batch_workspace_bytes", "solve_rve_batch", "rve_autotune", "rve_load_tuning", "rve_tuned_tiles", "rve_last_error",
-               "rve_status_string")
+               "rve_last_solve_info", "rve_status_string")
 
 
 class RveError(RuntimeError):
@@ -107,6 +107,8 @@ def load_library():
     lib.rve_tuned_tiles.restype = ctypes.c_int32
     lib.rve_last_error.argtypes = []
     lib.rve_last_error.restype = ctypes.c_char_p
+    lib.rve_last_solve_info.argtypes = [dp, ip, ctypes.c_int32]
+    lib.rve_last_solve_info.restype = ctypes.c_int32
     lib.rve_status_string.argtypes = [ctypes.c_int]
     lib.rve_status_string.restype = ctypes.c_char_p
     _lib = lib
@@ -161,6 +163,15 @@ def tuned_tiles(n, precision: int = FP32_MIXED, L=(1.0, 1.0, 1.0)):
 
 def load_tuning(path: str) -> int:
     return int(load_library().rve_load_tuning(path.encode()))
+
+
+def last_solve_info(max_cases: int = 64) -> dict:
+    """Start of the last solve on this thread: initial relative residual and warm-start rejection per case."""
+    r0 = np.zeros(max_cases)
+    rej = np.zeros(max_cases, dtype=np.int32)
+    n = load_library().rve_last_solve_info(_dp(r0), rej.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), max_cases)
+    n = min(int(n), max_cases)
+    return dict(initial_rel_residual=r0[:n].copy(), warm_rejected=rej[:n].astype(bool))
 
 
 def status_string(s: int) -> str:

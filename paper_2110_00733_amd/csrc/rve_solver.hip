@@ -205,7 +205,8 @@ struct CaseInfo {
   int active;         // this case still needs an inner sweep
   int iters;          // MINRES iterations summed over sweeps
   int status;         // worst inner status
-  int pad;
+  int warm_rejected;  // the warm start was replaced by zero
+  double r0;          // ||b - A x0|| of the start (before a rejected warm start is dropped)
 };
 
 // Start an inner MINRES on A d = r with u_1 = r (partials hold ||u_1||^2).
@@ -332,6 +333,27 @@ __global__ void k_residual_update(CaseInfo* ci, const double* sums, int nc, doub
   const bool conv = ci[cs].bnorm == 0.0 || ci[cs].rnorm <= tol * ci[cs].bnorm;
   const bool bad = ci[cs].status == RVE_ENONFINITE || ci[cs].status == RVE_BREAKDOWN;
   ci[cs].active = (!conv && !bad && ci[cs].iters < max_iter) ? 1 : 0;
+}
+
+// A warm start that does not reduce the residual below ||b|| is dropped: x = 0, r = b (the zero
+// start, bit for bit).  Grid (blocks, nc).
+__global__ void k_warm_fallback(double* x64, double* r64, const double* b64, CaseInfo* ci, long long n6) {
+  const int cs = blockIdx.y;
+  if (!(ci[cs].bnorm > 0.0 && ci[cs].rnorm >= ci[cs].bnorm)) return;
+  const long long off = (long long)cs * n6;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n6; i += (long long)gridDim.x * blockDim.x) {
+    x64[off + i] = 0.0;
+    r64[off + i] = b64[off + i];
+  }
+}
+// after k_warm_fallback: record the rejection, the residual is now ||b||
+__global__ void k_residual_update_fallback(CaseInfo* ci, int nc) {
+  const int cs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cs >= nc) return;
+  ci[cs].r0 = ci[cs].rnorm;
+  if (!(ci[cs].bnorm > 0.0 && ci[cs].rnorm >= ci[cs].bnorm)) return;
+  ci[cs].warm_rejected = 1;
+  ci[cs].rnorm = ci[cs].bnorm;
 }
 
 // Post-processing: sigma = C(x) (Ebar + eps) in FP64, write strain/stress in the output type,
@@ -560,6 +582,11 @@ static Tables<T> tables_at(const Plan& pl, char* base) {
 
 // Text of the last HIP failure seen by this library (for diagnostics; see rve_last_error()).
 static thread_local char g_last_error[256] = "";
+struct LastInfo {
+  double r0_rel = 0.0;
+  int warm_rejected = 0;
+};
+static thread_local std::vector<LastInfo> g_last_info;  // per case, last solve_rve on this thread
 static void note_hip_error(hipError_t e, const char* expr, int line) {
   snprintf(g_last_error, sizeof(g_last_error), "%s (%d) in '%s' at rve_solver.hip:%d", hipGetErrorString(e), (int)e,
            expr, line);
@@ -922,6 +949,15 @@ const char* rve_profile_kind_name(int32_t k) { return (k >= 0 && k < prof::NKIND
 
 const char* rve_last_error(void) { return g_last_error; }
 
+int32_t rve_last_solve_info(double* initial_rel_residual, int32_t* warm_rejected, int32_t max_cases) {
+  const int n = (int)g_last_info.size();
+  for (int c = 0; c < std::min(n, (int)max_cases); ++c) {
+    if (initial_rel_residual) initial_rel_residual[c] = g_last_info[c].r0_rel;
+    if (warm_rejected) warm_rejected[c] = g_last_info[c].warm_rejected;
+  }
+  return n;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------- autotuner
@@ -1281,7 +1317,8 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
     hci[c].rnorm = hb[c];
     hci[c].iters = 0;
     hci[c].status = 0;
-    hci[c].pad = 0;
+    hci[c].warm_rejected = 0;
+    hci[c].r0 = hb[c];
     hci[c].active = 1;
   }
   // A right-hand side at the rounding level of the transforms of a constant field counts as zero:
@@ -1328,6 +1365,8 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
     hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
     hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
                        opt->max_iter);
+    hipLaunchKernelGGL(k_warm_fallback, dim3(1024, nc), dim3(256), 0, s, x64, r64, b64, dci, n6);
+    hipLaunchKernelGGL(k_residual_update_fallback, dim3((nc + 63) / 64), dim3(64), 0, s, dci, nc);
   } else {
     hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, x64, n6 * nc);
     HIPCHK(hipMemcpyAsync(r64, b64, sizeof(double) * n6 * nc, hipMemcpyDeviceToDevice, s));
@@ -1424,6 +1463,11 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
     else if (hci[c].bnorm > 0 && !(rel_residual[c] <= opt->tol) && worst_warn == RVE_OK) worst_warn = RVE_NOT_CONVERGED;
   }
   rve_status worst = worst_err != RVE_OK ? worst_err : worst_warn;
+  g_last_info.assign(nc, LastInfo{});
+  for (int c = 0; c < nc; ++c) {
+    g_last_info[c].r0_rel = hci[c].bnorm > 0 ? hci[c].r0 / hci[c].bnorm : 0.0;
+    g_last_info[c].warm_rejected = hci[c].warm_rejected;
+  }
   return worst;
 }
 

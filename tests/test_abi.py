@@ -19,9 +19,14 @@ def _rve():
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "rve.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", txt)) - {"sizeof"})
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", txt)) - {"sizeof"}
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -31,7 +36,8 @@ def test_library_exports_every_declared_symbol():
     assert "solve_rve" in names and "rve_apply" in names
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert sorted(rve.ABI_SYMBOLS) == names
+    from paper_2110_00733_amd import nn
+    assert sorted(rve.ABI_SYMBOLS + nn.NN_ABI_SYMBOLS) == names
 
 
 def test_supported_lengths():
@@ -84,3 +90,33 @@ def test_solve_without_gpu_raises_not_falls_back():
     rve = _rve()
     with pytest.raises(RuntimeError):
         rve.solve(torch.zeros(4, 4, 4), np.eye(6), np.eye(6))
+
+
+def test_nn_entry_points_validate_before_launch():
+    """rve_nn_* reject bad sizes, strides and pointers on the host (nothing is launched)."""
+    rve = _rve()
+    from paper_2110_00733_amd import nn
+    lib = nn.nnlib()
+    fake = nn.ctypes.c_void_p(4096)
+    dims = nn._i32(1, 4, 4, 4)
+    assert lib.rve_nn_wgrad_workspace_bytes(16, 16, dims, 3) == 4 * (27 * 16 * 16 + 16)  # one chunk
+    assert lib.rve_nn_wgrad_workspace_bytes(16, 16, dims, 2) == 0
+    assert lib.rve_nn_wgrad_workspace_bytes(16, 16, nn._i32(1, 0, 4, 4), 3) == 0
+    EINVAL, ENOMEM = rve.RVE_EINVAL, rve.RVE_ENOMEM
+    conv = lambda cin, xs, xo, cout, ys, k=3, d=dims: lib.rve_nn_conv3d(fake, cin, xs, xo, fake, None, cout, fake, ys,
+                                                                         0, 0, 0, None, 0, 0, d, k, None)
+    assert conv(20, 20, 0, 16, 16) == EINVAL          # cin not a multiple of 16
+    assert conv(16, 16, 0, 80, 80) == EINVAL          # no kernel for 5 output tiles
+    assert conv(16, 16, 0, 272, 272) == EINVAL        # cout above 256
+    assert conv(16, 16, 4, 16, 16) == EINVAL          # slice exceeds the stride
+    assert conv(16, 18, 2, 16, 16) == EINVAL          # misaligned operand loads
+    assert conv(16, 16, 0, 16, 16, k=5) == EINVAL
+    assert conv(16, 16, 0, 16, 16, d=nn._i32(1, 4, -1, 4)) == EINVAL
+    assert lib.rve_nn_conv3d_wgrad(fake, 16, 16, 0, fake, 16, 16, 0, fake, None, dims, 3, fake, 16, None) == ENOMEM
+    assert lib.rve_nn_conv3d_wgrad(fake, 16, 16, 0, fake, 16, 16, 0, fake, None, dims, 3, None, 1 << 30, None) == ENOMEM
+    assert lib.rve_nn_resample(0, fake, 8, 8, 0, fake, 8, 0, None, 0, 0, nn._i32(1, 3, 4, 4), None) == EINVAL
+    assert lib.rve_nn_resample(1, fake, 8, 8, 0, fake, 8, 0, None, 0, 0, dims, None) == EINVAL  # needs a mask
+    assert lib.rve_nn_resample(7, fake, 8, 8, 0, fake, 8, 0, None, 0, 0, dims, None) == EINVAL
+    assert lib.rve_nn_restrict(fake, nn._i32(64, 64, 60), 8, fake, None) == EINVAL
+    assert lib.rve_nn_prolong(fake, 32, nn._i32(4, 4, 4), 2, fake, fake, None) == EINVAL  # needs 36 channels
+    assert lib.rve_nn_adam(fake, fake, fake, fake, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, 0.0, None) == EINVAL

@@ -1,0 +1,416 @@
+"""GPU parity of the learned warm start's kernels (include/rve_nn.h) with the FP64 network oracle.
+
+BF16 operands are drawn on the host, rounded to BF16 once, and the same rounded values go to the
+oracle in float64.  FP32-output convolutions and gradients then differ from the oracle only by FP32
+accumulation order (bound 1e-5 of sum |terms|); BF16 outputs by one rounding (2^-8 relative).
+The whole network keeps every activation in BF16, so its outputs and gradients are compared in
+relative norm against bounds measured with margin (forward 2e-2, gradients 5e-2 per layer, 2e-2
+over all parameters).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import nn_oracle as nno
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_00733_amd import nn
+    return torch, nn
+
+
+def _bf16(torch, a):
+    """(device bf16 tensor, float64 numpy of the same rounded values)"""
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16)
+    return t.cuda(), t.double().numpy()
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _conv_gpu(torch, nn, x_t, cin, xs, xo, w_t, b_t, cout, y_t, ys, yo, y_f32, relu, dims, k, mask=None, ms=0, mo=0):
+    st = nn.nnlib().rve_nn_conv3d(nn._p(x_t), cin, xs, xo, nn._p(w_t), nn._p(b_t), cout, nn._p(y_t), ys, yo,
+                                  y_f32, relu, nn._p(mask), ms, mo, nn._i32(*dims), k, _stream(torch))
+    assert st == 0
+    torch.cuda.synchronize()
+
+
+CONV_CASES = [
+    # B, (n0, n1, n2), cin, cout, ksize, x_stride, x_off, y_stride, y_off
+    (1, (5, 6, 7), 16, 16, 3, 16, 0, 16, 0),
+    (2, (4, 4, 4), 32, 48, 3, 48, 16, 64, 8),
+    (1, (8, 8, 8), 192, 64, 3, 192, 0, 64, 0),
+    (1, (3, 2, 5), 48, 256, 3, 48, 0, 256, 0),
+    (2, (6, 6, 6), 16, 48, 1, 16, 0, 48, 0),
+    (1, (1, 1, 1), 128, 128, 3, 128, 0, 128, 0),
+]
+
+
+@pytest.mark.parametrize("case", CONV_CASES)
+def test_conv3d_forward_matches_oracle(case):
+    torch, nn = _setup()
+    B, n, cin, cout, k, xs, xo, ys, yo = case
+    rng = np.random.default_rng(hash(case) % 2 ** 32)
+    taps = 27 if k == 3 else 1
+    V = B * int(np.prod(n))
+    x_t, x64 = _bf16(torch, rng.standard_normal((V, xs)))
+    w_t, w64 = _bf16(torch, rng.standard_normal((taps, cout, cin)) / np.sqrt(taps * cin))
+    b = rng.standard_normal(cout).astype(np.float32)
+    b_t = torch.from_numpy(b).cuda()
+    xin = x64[:, xo:xo + cin].reshape((B,) + n + (cin,))
+    ref = nno.conv3d(xin, w64, b.astype(np.float64), k).reshape(V, cout)
+    scale = nno.conv3d(np.abs(xin), np.abs(w64), np.abs(b).astype(np.float64), k).reshape(V, cout)
+    # FP32 output, no activation
+    y = torch.full((V, ys), 7.0, dtype=torch.float32, device="cuda")
+    _conv_gpu(torch, nn, x_t, cin, xs, xo, w_t, b_t, cout, y, ys, yo, 1, 0, (B,) + n, k)
+    yh = y.cpu().double().numpy()
+    assert np.all(np.abs(yh[:, yo:yo + cout] - ref) <= 1e-5 * scale + 1e-30)
+    assert np.all(yh[:, :yo] == 7.0) and np.all(yh[:, yo + cout:] == 7.0)  # outside the slice untouched
+    # BF16 output with ReLU
+    yb = torch.zeros((V, ys), dtype=torch.bfloat16, device="cuda")
+    _conv_gpu(torch, nn, x_t, cin, xs, xo, w_t, b_t, cout, yb, ys, yo, 0, 1, (B,) + n, k)
+    ybh = yb.cpu().double().numpy()[:, yo:yo + cout]
+    rr = np.maximum(ref, 0)
+    assert np.all(np.abs(ybh - rr) <= 2.0 ** -8 * np.abs(rr) + 1e-5 * scale + 1e-30)
+    assert np.all(ybh[ref < -1e-4 * scale] == 0)
+
+
+def test_conv3d_mask_and_data_gradient():
+    """dx of a convolution = the flipped-weight convolution of dy, masked by a ReLU output."""
+    torch, nn = _setup()
+    rng = np.random.default_rng(5)
+    B, n, cin, cout = 2, (4, 6, 4), 48, 32
+    V = B * int(np.prod(n))
+    dy_t, dy64 = _bf16(torch, rng.standard_normal((V, cout)))
+    w_t, w64 = _bf16(torch, rng.standard_normal((27, cout, cin)) / 20)
+    act = np.maximum(rng.standard_normal((V, cin)), 0)  # a ReLU output: about half zero
+    act_t, act64 = _bf16(torch, act)
+    wd = torch.empty_like(w_t)
+    assert nn.nnlib().rve_nn_flip_weights(nn._p(w_t), nn._p(wd), cin, cout, 3, _stream(torch)) == 0
+    dx = torch.zeros((V, cin), dtype=torch.float32, device="cuda")
+    _conv_gpu(torch, nn, dy_t, cout, cout, 0, wd, None, cin, dx, cin, 0, 1, 0, (B,) + n, 3, mask=act_t, ms=cin, mo=0)
+    x0 = np.zeros((B,) + n + (cin,))
+    ref, _, _ = nno.conv3d_backward(x0, w64, dy64.reshape((B,) + n + (cout,)), 3)
+    ref = ref.reshape(V, cin) * (act64 > 0)
+    scale, _, _ = nno.conv3d_backward(x0, np.abs(w64), np.abs(dy64).reshape((B,) + n + (cout,)), 3)
+    got = dx.cpu().double().numpy()
+    assert np.all(np.abs(got - ref) <= 1e-5 * scale.reshape(V, cin) + 1e-30)
+    assert np.all(got[act64 == 0] == 0)
+
+
+WGRAD_CASES = [
+    # B, n, cin, cout, ksize, x_stride, x_off, dy_stride, dy_off
+    (2, (16, 16, 16), 16, 16, 3, 16, 0, 16, 0),
+    (1, (5, 7, 6), 48, 16, 3, 48, 0, 48, 32),
+    (2, (4, 4, 4), 192, 64, 3, 192, 0, 64, 0),
+    (1, (8, 8, 8), 16, 48, 1, 16, 0, 48, 0),
+    (3, (2, 2, 2), 64, 128, 3, 80, 16, 128, 0),
+]
+
+
+@pytest.mark.parametrize("case", WGRAD_CASES)
+def test_conv3d_weight_gradient_matches_oracle(case):
+    torch, nn = _setup()
+    B, n, cin, cout, k, xs, xo, ds, do = case
+    rng = np.random.default_rng(hash(case) % 2 ** 32)
+    taps = 27 if k == 3 else 1
+    V = B * int(np.prod(n))
+    x_t, x64 = _bf16(torch, rng.standard_normal((V, xs)))
+    dy_t, dy64 = _bf16(torch, rng.standard_normal((V, ds)))
+    dims = nn._i32(B, *n)
+    lib = nn.nnlib()
+    wsb = lib.rve_nn_wgrad_workspace_bytes(cin, cout, dims, k)
+    assert wsb > 0
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    dw = torch.zeros(taps * cout * cin, dtype=torch.float32, device="cuda")
+    db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+    assert lib.rve_nn_conv3d_wgrad(nn._p(x_t), cin, xs, xo, nn._p(dy_t), cout, ds, do, nn._p(dw), nn._p(db), dims, k,
+                                   nn._p(ws), wsb - 1, _stream(torch)) == -4  # workspace too small
+    assert lib.rve_nn_conv3d_wgrad(nn._p(x_t), cin, xs, xo, nn._p(dy_t), cout, ds, do, nn._p(dw), nn._p(db), dims, k,
+                                   nn._p(ws), wsb, _stream(torch)) == 0
+    torch.cuda.synchronize()
+    xin = x64[:, xo:xo + cin].reshape((B,) + n + (cin,))
+    dyin = dy64[:, do:do + cout].reshape((B,) + n + (cout,))
+    _, rw, rb = nno.conv3d_backward(xin, np.zeros((taps, cout, cin)), dyin, k)
+    _, sw, sb = nno.conv3d_backward(np.abs(xin), np.zeros((taps, cout, cin)), np.abs(dyin), k)
+    gw = dw.cpu().double().numpy().reshape(taps, cout, cin)
+    assert np.all(np.abs(gw - rw) <= 1e-5 * sw + 1e-30)
+    assert np.all(np.abs(db.cpu().double().numpy() - rb) <= 1e-5 * sb + 1e-30)
+    # deterministic: a second call gives the same bits
+    dw2 = torch.zeros_like(dw)
+    assert lib.rve_nn_conv3d_wgrad(nn._p(x_t), cin, xs, xo, nn._p(dy_t), cout, ds, do, nn._p(dw2), None, dims, k,
+                                   nn._p(ws), wsb, _stream(torch)) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(dw, dw2)
+
+
+def test_resampling_matches_oracle():
+    torch, nn = _setup()
+    rng = np.random.default_rng(8)
+    lib = nn.nnlib()
+    B, n, c = 2, (4, 6, 8), 24
+    Vf = B * int(np.prod(n))
+    nc = tuple(v // 2 for v in n)
+    Vc = B * int(np.prod(nc))
+    s = _stream(torch)
+
+    def bf(a):
+        return torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).double().numpy()
+
+    x_t, x64 = _bf16(torch, rng.standard_normal((Vf, 32)))
+    y = torch.zeros((Vc, c), dtype=torch.bfloat16, device="cuda")
+    assert lib.rve_nn_resample(nn.POOL2, nn._p(x_t), c, 32, 8, nn._p(y), c, 0, None, 0, 0, nn._i32(B, *n), s) == 0
+    ref = nno.pool2(x64[:, 8:8 + c].reshape((B,) + n + (c,))).reshape(Vc, c)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(y.cpu().double().numpy() - bf(ref))) <= 2.0 ** -8 * np.max(np.abs(ref))
+    # upsample and its adjoint
+    u_t, u64 = _bf16(torch, rng.standard_normal((Vc, c)))
+    up = torch.zeros((Vf, 40), dtype=torch.bfloat16, device="cuda")
+    assert lib.rve_nn_resample(nn.UP2, nn._p(u_t), c, c, 0, nn._p(up), 40, 16, None, 0, 0, nn._i32(B, *nc), s) == 0
+    torch.cuda.synchronize()
+    ref = nno.up2(u64.reshape((B,) + nc + (c,))).reshape(Vf, c)
+    assert np.array_equal(up.cpu().double().numpy()[:, 16:16 + c], ref)
+    g_t, g64 = _bf16(torch, rng.standard_normal((Vf, c)))
+    ub = torch.zeros((Vc, c), dtype=torch.bfloat16, device="cuda")
+    assert lib.rve_nn_resample(nn.UP2_BWD, nn._p(g_t), c, c, 0, nn._p(ub), c, 0, None, 0, 0, nn._i32(B, *nc), s) == 0
+    torch.cuda.synchronize()
+    ref = nno.up2_backward(g64.reshape((B,) + n + (c,))).reshape(Vc, c)
+    assert np.max(np.abs(ub.cpu().double().numpy() - ref)) <= 2.0 ** -8 * np.max(np.abs(ref)) + 1e-6
+    # pooling backward, accumulated into an existing gradient and masked
+    prev_t, prev64 = _bf16(torch, rng.standard_normal((Vf, c)))
+    m_t, m64 = _bf16(torch, np.maximum(rng.standard_normal((Vf, c)), 0))
+    d_t, d64 = _bf16(torch, rng.standard_normal((Vc, c)))
+    assert lib.rve_nn_resample(nn.POOL2_BWD_ACC, nn._p(d_t), c, c, 0, nn._p(prev_t), c, 0, nn._p(m_t), c, 0,
+                               nn._i32(B, *n), s) == 0
+    torch.cuda.synchronize()
+    ref = np.where(m64 > 0, prev64 + nno.pool2_backward(d64.reshape((B,) + nc + (c,))).reshape(Vf, c), prev64)
+    got = prev_t.cpu().double().numpy()
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-30)
+    # odd fine dims are rejected before any launch
+    assert lib.rve_nn_resample(nn.POOL2, nn._p(x_t), c, 32, 8, nn._p(y), c, 0, None, 0, 0, nn._i32(1, 3, 4, 4),
+                               s) == -1
+
+
+def test_loss_adam_and_conversions_match_oracle():
+    torch, nn = _setup()
+    rng = np.random.default_rng(12)
+    lib = nn.nnlib()
+    s = _stream(torch)
+    B, n = 2, (4, 4, 6)
+    nv = int(np.prod(n))
+    pred = rng.standard_normal((B * nv, 48)).astype(np.float32)
+    target = rng.standard_normal((B, 36, nv)).astype(np.float32)
+    phi = rng.uniform(0, 1, (B, nv)).astype(np.float32)
+    phi[:, ::3] = 0.0
+    inv = 1.0 / (36 * float(np.sum(0.1 + phi.astype(np.float64))))
+    pr_t, tg_t, ph_t = (torch.from_numpy(a).cuda() for a in (pred, target, phi))
+    dp = torch.zeros((B * nv, 48), dtype=torch.bfloat16, device="cuda")
+    part = torch.zeros(64, dtype=torch.float64, device="cuda")
+    phi[0, :5] = 1.0
+    ph_t = torch.from_numpy(phi).cuda()
+    w3 = (0.1, 1.0, 3.0)
+    assert lib.rve_nn_loss(nn._p(pr_t), 48, nn._p(tg_t), 36, nn._p(ph_t), (ctypes.c_float * 3)(*w3), nv, B,
+                           ctypes.c_float(inv), nn._p(dp), 48, nn._p(part), 64, s) == 0
+    torch.cuda.synchronize()
+    tl = np.moveaxis(target.astype(np.float64), 1, -1).reshape((B,) + n + (36,))
+    L, g = nno.weighted_loss(pred.astype(np.float64).reshape((B,) + n + (48,)), tl,
+                             phi.astype(np.float64).reshape((B,) + n), w3, inv)
+    assert inv * float(part.cpu().numpy().sum()) == pytest.approx(L, rel=1e-5)
+    gg = g.reshape(B * nv, 48)
+    assert np.all(np.abs(dp.cpu().double().numpy() - gg) <= 2.0 ** -8 * np.abs(gg) + 1e-12)
+    # Adam
+    N = 5000
+    p, gr, m, v = (rng.standard_normal(N).astype(np.float32) for _ in range(4))
+    v = np.abs(v)
+    tp, tg, tm, tv = (torch.from_numpy(a.copy()).cuda() for a in (p, gr, m, v))
+    pb = torch.zeros(N, dtype=torch.bfloat16, device="cuda")
+    assert lib.rve_nn_adam(nn._p(tp), nn._p(tg), nn._p(tm), nn._p(tv), nn._p(pb), N, ctypes.c_float(1e-3),
+                           ctypes.c_float(0.9), ctypes.c_float(0.999), ctypes.c_float(1e-8), 3, ctypes.c_float(0.01),
+                           s) == 0
+    torch.cuda.synchronize()
+    rp, rm, rv = nno.adam_step(p.astype(np.float64), gr.astype(np.float64), m.astype(np.float64),
+                               v.astype(np.float64), 1e-3, 0.9, 0.999, 1e-8, 3, weight_decay=0.01)
+    assert np.allclose(tp.cpu().double().numpy(), rp, rtol=1e-6, atol=1e-8)
+    assert np.allclose(tm.cpu().double().numpy(), rm, rtol=1e-5, atol=1e-7)
+    assert np.allclose(tv.cpu().double().numpy(), rv, rtol=1e-5, atol=1e-7)
+    # BF16 copies round to nearest even, like torch's conversion
+    assert torch.equal(pb.cpu(), tp.cpu().to(torch.bfloat16))
+    a = torch.from_numpy(rng.standard_normal(999).astype(np.float32) * 1e3).cuda()
+    b = torch.zeros(999, dtype=torch.bfloat16, device="cuda")
+    assert lib.rve_nn_to_bf16(nn._p(a), nn._p(b), 999, s) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(b.cpu(), a.cpu().to(torch.bfloat16))
+
+
+def test_pack_input():
+    torch, nn = _setup()
+    rng = np.random.default_rng(14)
+    phi = rng.uniform(0, 1, (3, 5 * 4 * 6)).astype(np.float32)
+    ex = rng.standard_normal((3, 7, 5 * 4 * 6)).astype(np.float32)
+    out = torch.full((3 * 120, 16), 5.0, dtype=torch.bfloat16, device="cuda")
+    lib = nn.nnlib()
+    assert lib.rve_nn_pack_input(nn._p(torch.from_numpy(phi).cuda()), nn._p(torch.from_numpy(ex).cuda()), 7,
+                                 nn._p(out), 16, 120, 3, _stream(torch)) == 0
+    torch.cuda.synchronize()
+    o = out.cpu().reshape(3, 120, 16)
+    assert torch.equal(o[..., 0], torch.from_numpy(phi).to(torch.bfloat16))
+    assert torch.equal(o[..., 1:8], torch.from_numpy(ex).to(torch.bfloat16).transpose(1, 2))
+    assert torch.all(o[..., 8:] == 0)
+    assert lib.rve_nn_pack_input(nn._p(torch.from_numpy(phi).cuda()), None, 16, nn._p(out), 16, 120, 3,
+                                 _stream(torch)) == -1
+
+
+def test_restrict_and_prolong_match_oracle():
+    torch, nn = _setup()
+    rng = np.random.default_rng(13)
+    lib = nn.nnlib()
+    s = _stream(torch)
+    phi = rng.uniform(0, 1, (16, 16, 16)).astype(np.float32)
+    pt = torch.from_numpy(phi).cuda()
+    co = torch.zeros((4, 4, 4), dtype=torch.float32, device="cuda")
+    assert lib.rve_nn_restrict(nn._p(pt), nn._i32(16, 16, 16), 4, nn._p(co), s) == 0
+    torch.cuda.synchronize()
+    assert np.allclose(co.cpu().double().numpy(), nno.restrict(phi.astype(np.float64), 4), atol=1e-6)
+    pred = rng.standard_normal((4 * 5 * 3, 48)).astype(np.float32)
+    E = rng.standard_normal(6)
+    for f in (1, 2, 3):
+        eps = torch.zeros((6, 4 * f, 5 * f, 3 * f), dtype=torch.float32, device="cuda")
+        Ed = torch.from_numpy(E).cuda()
+        assert lib.rve_nn_prolong(nn._p(torch.from_numpy(pred).cuda()), 48, nn._i32(4, 5, 3), f, nn._p(Ed),
+                                  nn._p(eps), s) == 0
+        torch.cuda.synchronize()
+        ref = nno.prolong(pred.astype(np.float64).reshape(4, 5, 3, 48), f, E)
+        assert np.allclose(eps.cpu().double().numpy(), ref, rtol=1e-5, atol=1e-5)
+
+
+def _net_and_oracle(seed, n=16, B=2):
+    torch, nn = _setup()
+    net = nn.WarmStartNet(seed=seed)
+    rng = np.random.default_rng(seed)
+    host = net.p32.cpu().numpy().copy()
+    for name, L in net.layers.items():
+        host[L["b"]:L["b"] + L["cout"]] = rng.standard_normal(L["cout"]) * 0.05
+    net.set_params(host)
+    phi = rng.uniform(0, 1, (B, n, n, n)).astype(np.float32)
+    phi[phi < 0.5] = 0.0
+    target = rng.standard_normal((B, 36, n ** 3)).astype(np.float32)
+    return torch, nn, net, phi, target
+
+
+def test_network_forward_and_gradients_match_oracle():
+    torch, nn, net, phi, target = _net_and_oracle(21)
+    B, n = phi.shape[0], phi.shape[1]
+    pt = torch.from_numpy(phi).cuda()
+    tt = torch.from_numpy(target).cuda()
+    inv = 1.0 / (36 * float(np.sum(0.1 + phi.astype(np.float64))))
+    net.pack(pt, n)
+    out = net.forward(B, n)
+    net.loss(B, n, tt, pt, (0.1, 1.0, 0.0), inv)
+    net.backward(B, n)
+    torch.cuda.synchronize()
+    params = net.params()
+    x = np.zeros((B, n, n, n, 16))
+    x[..., 0] = torch.from_numpy(phi).to(torch.bfloat16).double().numpy()
+    ref_out, cache = nno.forward(params, x)
+    got = out.cpu().double().numpy().reshape(ref_out.shape)
+    fwd_err = np.linalg.norm(got - ref_out) / np.linalg.norm(ref_out)
+    print(f"forward rel err {fwd_err:.2e}")
+    assert fwd_err < 2e-2, fwd_err
+    tl = np.moveaxis(target.astype(np.float64), 1, -1).reshape(B, n, n, n, 36)
+    _, dout = nno.weighted_loss(ref_out, tl, phi.astype(np.float64), (0.1, 1.0, 0.0), inv)
+    ref_g = nno.backward(params, cache, dout)
+    g = net.grads()
+    num = den = 0.0
+    for name in ref_g:
+        for i in (0, 1):
+            e = np.linalg.norm(g[name][i] - ref_g[name][i])
+            r = np.linalg.norm(ref_g[name][i])
+            print(f"{name}[{'wb'[i]}] rel err {e / max(r, 1e-300):.2e}")
+            assert e <= 5e-2 * r + 1e-12, (name, i, e / r)
+            num += e * e
+            den += r * r
+    print(f"all-parameter gradient rel err {np.sqrt(num / den):.2e}")
+    assert np.sqrt(num / den) < 2e-2
+
+
+def test_training_reduces_loss():
+    """Adam steps on the GPU fit a target that is a fixed function of phi."""
+    torch, nn, net, phi, _ = _net_and_oracle(3, n=16, B=2)
+    B, n = phi.shape[0], phi.shape[1]
+    pt = torch.from_numpy(phi).cuda()
+    target = np.stack([np.stack([phi[b].reshape(-1) * (0.5 + 0.05 * c) for c in range(36)]) for b in range(B)])
+    tt = torch.from_numpy(target.astype(np.float32)).cuda()
+    inv = 1.0 / (36 * float(np.sum(0.1 + phi.astype(np.float64))))
+    losses = []
+    for it in range(150):
+        part = net.train_step(pt, tt, inv, lr=2e-3)
+        if it % 10 == 0 or it == 149:
+            losses.append(inv * float(part.cpu().numpy().sum()))
+    assert all(np.isfinite(losses))
+    assert losses[-1] < 0.25 * losses[0], losses
+    assert all(b < a for a, b in zip(losses[4:], losses[5:])), losses
+
+
+def test_warm_start_rejected_when_it_does_not_help():
+    """A start whose residual is not below ||b|| is dropped: the solve equals the zero-start solve."""
+    import torch
+    import lattice_inputs as li
+    import paper_2110_00733_amd as rve
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    phi, _ = li.octet_phase_map(16, 0.2)
+    pt = torch.from_numpy(phi).cuda()
+    C = li.isotropic_mandel(1.0, 0.3)
+    E = li.uniaxial_strain(1e-3)
+    ref = rve.solve(pt, C, E, tol=1e-6)
+    assert rve.last_solve_info()["initial_rel_residual"][0] == pytest.approx(1.0)
+    bad = torch.from_numpy(np.random.default_rng(0).standard_normal((1, 6, 16, 16, 16)).astype(np.float32)).cuda()
+    out = rve.solve(pt, C, E, tol=1e-6, eps0=bad)
+    info = rve.last_solve_info()
+    assert info["warm_rejected"][0] and info["initial_rel_residual"][0] > 1.0
+    assert out["iterations"][0] == ref["iterations"][0]
+    assert np.array_equal(out["eff_stress"], ref["eff_stress"])
+    assert torch.equal(out["strain"], ref["strain"])
+    # the converged field itself is an excellent start: accepted, and almost no iterations remain
+    good = rve.solve(pt, C, E, tol=1e-6, eps0=ref["strain"])
+    info = rve.last_solve_info()
+    assert not info["warm_rejected"][0] and info["initial_rel_residual"][0] < 1e-5
+    assert good["iterations"][0] <= 30
+
+
+def test_trained_warm_start_on_heldout_lattice():
+    """The committed network on a 64^3 defect lattice it never saw: its start is accepted with a much
+    smaller initial residual than the zero start (about 0.15), the solve still converges to the same
+    effective stiffness, and the iteration count stays within a few percent of the zero start (the
+    remaining error sits in the slow surface-voxel modes)."""
+    import torch
+    import lattice_inputs as li
+    import paper_2110_00733_amd as rve
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_00733_amd.nn import WarmStartNet
+    from paper_2110_00733_amd.warmstart_train import DEFAULT_WEIGHTS, make_phi
+    net = WarmStartNet().load(DEFAULT_WEIGHTS)
+    assert net.meta["grid"] == 64
+    phi = torch.from_numpy(make_phi(334)).cuda()  # first seed after the training and validation sets
+    C = li.isotropic_mandel(1.0, 0.3)
+    E = li.unit_mandel_cases()
+    zero = rve.solve(phi, C, E, tol=1e-6, want_stress=False)
+    warm = rve.solve(phi, C, E, tol=1e-6, want_stress=False, eps0=net.predict(phi, E, grid=64))
+    info = rve.last_solve_info()
+    print(f"iterations zero {zero['iterations'].sum()} learned {warm['iterations'].sum()}, "
+          f"initial residual {info['initial_rel_residual']}")
+    assert not info["warm_rejected"].any()
+    assert info["initial_rel_residual"].max() < 0.3
+    assert warm["status"] == 0 and warm["rel_residual"].max() <= 1e-6
+    Cz, Cw = zero["eff_stress"], warm["eff_stress"]
+    assert np.max(np.abs(Cz - Cw)) <= 2e-5 * np.max(np.abs(Cz))
+    ratio = warm["iterations"].sum() / zero["iterations"].sum()
+    assert 0.8 < ratio < 1.1, ratio

@@ -119,10 +119,10 @@ def test_unet_backward_finite_differences():
 
     def loss(params):
         out, _ = nn.forward(params, x)
-        return nn.weighted_loss(out, target, phi, 0.1, inv)[0]
+        return nn.weighted_loss(out, target, phi, (0.1, 1.0, 0.5), inv)[0]
 
     out, cache = nn.forward(p, x)
-    L, dout = nn.weighted_loss(out, target, phi, 0.1, inv)
+    L, dout = nn.weighted_loss(out, target, phi, (0.1, 1.0, 0.5), inv)
     grads = nn.backward(p, cache, dout)
     # small enough that no ReLU pre-activation crosses zero along the probe for these seeds
     h = 1e-7
@@ -145,19 +145,25 @@ def test_weighted_loss_gradient():
     pred = rng.standard_normal((2, 2, 3, 2, 48))
     target = rng.standard_normal((2, 2, 3, 2, 36))
     phi = rng.uniform(0, 1, (2, 2, 3, 2))
-    L, g = nn.weighted_loss(pred, target, phi, 0.25, 0.01)
+    phi[0, 0, 0, :] = [0.0, 1.0]
+    w3 = (0.25, 1.0, 2.0)
+    L, g = nn.weighted_loss(pred, target, phi, w3, 0.01)
     assert np.all(g[..., 36:] == 0)
     d = rng.standard_normal(pred.shape)
-    fd = _dd(lambda t: nn.weighted_loss(t, target, phi, 0.25, 0.01)[0], pred, d, 1e-4)
+    fd = _dd(lambda t: nn.weighted_loss(t, target, phi, w3, 0.01)[0], pred, d, 1e-4)
     assert abs(fd - np.sum(g * d)) < 1e-9
-    # a perfect prediction has zero loss, and void voxels only count with the void weight
+    # a perfect prediction has zero loss
     p2 = pred.copy()
     p2[..., :36] = target
-    assert nn.weighted_loss(p2, target, phi, 0.25, 0.01)[0] == 0.0
+    assert nn.weighted_loss(p2, target, phi, w3, 0.01)[0] == 0.0
+    # one unit error in one voxel costs that voxel's weight: void 0.25, full 1.25, partial 0.25 + phi + 2
     one = np.zeros_like(pred)
-    one[0, 0, 0, 0, 0] = 1.0
-    L0 = nn.weighted_loss(one, np.zeros_like(target), np.zeros_like(phi), 0.25, 1.0)[0]
-    assert L0 == pytest.approx(0.25)
+    for ph, w in ((0.0, 0.25), (1.0, 1.25), (0.375, 2.625)):
+        one[:] = 0.0
+        one[0, 0, 0, 0, 0] = 1.0
+        phi1 = np.zeros_like(phi)
+        phi1[0, 0, 0, 0] = ph
+        assert nn.weighted_loss(one, np.zeros_like(target), phi1, w3, 1.0)[0] == pytest.approx(w)
 
 
 def test_adam_closed_forms():
