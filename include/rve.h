@@ -168,8 +168,9 @@ void rve_profile_reset(void);
 int32_t rve_profile_read(double* total_ms, int64_t* launches, int32_t max_kinds);
 const char* rve_profile_kind_name(int32_t kind);
 
-/* Autotuner.  Times the operator apply for every admissible tile width of each pass kind (P3 pencils
- * per block, P2/P4 rows per block, P1/P5 rows per block; coordinate descent, HIP events on
+/* Autotuner.  Times the operator apply for the P3 component split (whole / halves) and every
+ * admissible tile width of each pass kind (P3 pencils per block, P2/P4 rows per block, P1/P5 rows
+ * per block; coordinate descent, HIP events on
  * hip_stream, 3 repetitions each) for this grid and precision, using the caller's workspace (at least
  * rve_workspace_bytes(grid, n_cases, default options of that precision)).  The fastest tiles are kept
  * in a process-wide table used by every later solve_rve / rve_apply on the same grid and precision,
@@ -182,9 +183,11 @@ rve_status rve_autotune(const rve_grid* grid, int32_t n_cases, int32_t precision
  * plans a grid).  Returns the number of entries loaded, -1 if the file cannot be read. */
 int32_t rve_load_tuning(const char* path);
 
-/* Tiles the next call on this grid and precision will use: tiles3 = {P1/P5 rows, P3 pencils,
- * P2/P4 rows}.  Returns 1 if they come from the tuner, 0 if they are the built-in heuristic. */
-int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles3);
+/* Tiles the next call on this grid and precision will use: tiles4 = {P1/P5 rows, P3 pencils,
+ * P2/P4 rows, P3 component split in effect (1: six components per thread, 2: three per thread over
+ * two block halves; the split needs each half to be whole 64-lane waves)}.  Returns 1 if they come
+ * from the tuner, 0 if they are the built-in heuristic. */
+int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles4);
 
 /* Text of the last HIP runtime failure behind an RVE_EDEVICE in this thread ("" if none). */
 const char* rve_last_error(void);

@@ -158,6 +158,7 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
 #pragma unroll
       for (int c = 0; c < 6; ++c) e[c][i] = row_ok ? xc[c * g.nvox + row + t + NB * i] : (T)0;
     }
+    // element by element, so that e[.][i] is dead once sg[.][i] and its <x, sigma> terms exist
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
 #pragma unroll
@@ -174,16 +175,20 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
         }
         sg[a][i] = sv * xs;
       }
-    }
-    if (partials) {
-#pragma unroll
-      for (int i = 0; i < NA; ++i)
+      if (partials) {
 #pragma unroll
         for (int a = 0; a < 6; ++a) acc += (double)e[a][i] * (double)sg[a][i];
+      }
     }
   }
   const int ws = tid % W, m = tid / W, M = blockDim.x / W;
   const int n1s = n1_0 + ws;
+  constexpr bool HOIST = sizeof(T) == 4;  // FP32: stage twiddles once, not once per component pair
+  cx<T> twv[HOIST ? NA : 1];
+  if (HOIST) {
+#pragma unroll
+    for (int a = 1; a < NA; ++a) twv[HOIST ? a : 0] = tw[(t * a) % N];
+  }
 #pragma unroll
   for (int pr = 0; pr < 3; ++pr) {
     cx<T> z[NA];
@@ -191,7 +196,7 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
     for (int i = 0; i < NA; ++i) z[i] = mk<T>(sg[2 * pr][i], sg[2 * pr + 1][i]);
     DFT<NA, -1, T>::run(z);
 #pragma unroll
-    for (int a = 1; a < NA; ++a) z[a] = cmul(z[a], tw[(t * a) % N]);
+    for (int a = 1; a < NA; ++a) z[a] = cmul(z[a], HOIST ? twv[HOIST ? a : 0] : tw[(t * a) % N]);
     lds_barrier();
 #pragma unroll
     for (int a = 0; a < NA; ++a) lds[(w * NA + a) * (NB + 1) + t] = z[a];
@@ -277,6 +282,40 @@ __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, const c
 }
 
 // ============================================================================ P3
+// Galerkin projection of one frequency (eq. galop): Ghat S = t (x) n + n (x) t - (n.t) n (x) n with
+// n = w/|w| and t = S n, applied to the Mandel components (S0..S5) in place and scaled by f (the 1/N
+// of the inverse transform); w = 0 gives 0.
+// 1/sqrt: the hardware reciprocal square root (1 ulp) in FP32, the correctly rounded form in FP64
+__device__ __forceinline__ float rnorm(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rnorm(double x) { return 1.0 / sqrt(x); }
+
+template <typename T>
+__device__ __forceinline__ void project_mandel(cx<T>& D0, cx<T>& D1, cx<T>& D2, cx<T>& D3, cx<T>& D4, cx<T>& D5,
+                                               T w0, T w1, T w2, T f) {
+  const T sq2 = (T)1.41421356237309504880168872420970, isq2 = (T)0.70710678118654752440084436210485;
+  const T nn = w0 * w0 + w1 * w1 + w2 * w2;
+  if (nn > (T)0) {
+    const T inv = rnorm(nn);
+    const T m0 = w0 * inv, m1 = w1 * inv, m2 = w2 * inv;
+    // t = f S n with the Mandel off-diagonals unscaled (S_ij = D_k / sqrt2), q = n . t
+    const T fh = f * isq2;
+    const cx<T> S00 = scl(D0, f), S11 = scl(D1, f), S22 = scl(D2, f);
+    const cx<T> S12 = scl(D3, fh), S02 = scl(D4, fh), S01 = scl(D5, fh);
+    const cx<T> t0 = scl(S00, m0) + scl(S01, m1) + scl(S02, m2);
+    const cx<T> t1 = scl(S01, m0) + scl(S11, m1) + scl(S12, m2);
+    const cx<T> t2 = scl(S02, m0) + scl(S12, m1) + scl(S22, m2);
+    const cx<T> q = scl(t0, m0) + scl(t1, m1) + scl(t2, m2);
+    D0 = scl(t0, (T)2 * m0) - scl(q, m0 * m0);
+    D1 = scl(t1, (T)2 * m1) - scl(q, m1 * m1);
+    D2 = scl(t2, (T)2 * m2) - scl(q, m2 * m2);
+    D3 = scl(scl(t1, m2) + scl(t2, m1) - scl(q, m1 * m2), sq2);
+    D4 = scl(scl(t0, m2) + scl(t2, m0) - scl(q, m0 * m2), sq2);
+    D5 = scl(scl(t0, m1) + scl(t1, m0) - scl(q, m0 * m1), sq2);
+  } else {
+    D0 = D1 = D2 = D3 = D4 = D5 = mk<T>(0, 0);
+  }
+}
+
 // grid (ceil(N1/W), K2, ncases), block W*NB threads, dyn. LDS NA*(NB*W+1) complex
 // All six components of the thread's pencil elements are loaded up front (maximum loads in flight)
 // and transformed in place in one register array D[c][.]: stage-A layout D[c][i] = x[t + NB i],
@@ -329,8 +368,7 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
     }
   }
 
-  // ---- per-frequency projection: Ghat S = t (x) n + n (x) t - (n.t) n (x) n, n = w/|w|
-  const T sq2 = (T)1.41421356237309504880168872420970, isq2 = (T)0.70710678118654752440084436210485;
+  // ---- per-frequency projection
   const int k1c = ok ? k1 : 0;
   const T s1 = ft.s[1][k1c], c1 = ft.c[1][k1c], s2 = ft.s[2][k2], c2 = ft.c[2][k2];
   const T c1c2 = c1 * c2, s1c2 = s1 * c2, c1s2 = c1 * s2;
@@ -348,27 +386,7 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
         } else {
           const T s0 = ft.s[0][k0], c0 = ft.c[0][k0];
           const T w0 = s0 * c1c2, w1 = c0 * s1c2, w2 = c0 * c1s2;
-          const T nn = w0 * w0 + w1 * w1 + w2 * w2;
-          if (nn > (T)0) {
-            const T inv = (T)1 / sqrt(nn);
-            const T m0 = w0 * inv, m1 = w1 * inv, m2 = w2 * inv;
-            const cx<T> S00 = D[0][e], S11 = D[1][e], S22 = D[2][e];
-            const cx<T> S12 = scl(D[3][e], isq2), S02 = scl(D[4][e], isq2), S01 = scl(D[5][e], isq2);
-            const cx<T> t0 = scl(S00, m0) + scl(S01, m1) + scl(S02, m2);
-            const cx<T> t1 = scl(S01, m0) + scl(S11, m1) + scl(S12, m2);
-            const cx<T> t2 = scl(S02, m0) + scl(S12, m1) + scl(S22, m2);
-            const cx<T> q = scl(t0, m0) + scl(t1, m1) + scl(t2, m2);
-            const T f = inv_total, fs = inv_total * sq2;
-            D[0][e] = scl(scl(t0, (T)2 * m0) - scl(q, m0 * m0), f);
-            D[1][e] = scl(scl(t1, (T)2 * m1) - scl(q, m1 * m1), f);
-            D[2][e] = scl(scl(t2, (T)2 * m2) - scl(q, m2 * m2), f);
-            D[3][e] = scl(scl(t1, m2) + scl(t2, m1) - scl(q, m1 * m2), fs);
-            D[4][e] = scl(scl(t0, m2) + scl(t2, m0) - scl(q, m0 * m2), fs);
-            D[5][e] = scl(scl(t0, m1) + scl(t1, m0) - scl(q, m0 * m1), fs);
-          } else {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) D[c][e] = mk<T>(0, 0);
-          }
+          project_mandel(D[0][e], D[1][e], D[2][e], D[3][e], D[4][e], D[5][e], w0, w1, w2, inv_total);
         }
       }
     }
@@ -386,6 +404,172 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
         if (a > 0) {
 #pragma unroll
           for (int u = 1; u < NB; ++u) D[c][j * NB + u] = cmulc(D[c][j * NB + u], tw[(u * a) % N]);
+        }
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) lds[a * RS + u * W + w] = D[c][j * NB + u];
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int a = 0; a < NA; ++a) D[c][a] = lds[a * RS + t * W + w];
+    DFT<NA, 1, T>::run(D[c]);
+    if (ok) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) base[c * pstride + (long long)(t + NB * i) * g.n1] = D[c][i];
+    }
+  }
+}
+
+// P3 with the six components split over two halves of the block (half h owns components 3h..3h+2),
+// halving the registers per thread.  W*NB must be a multiple of the wave size (64) so that the half
+// index is uniform per wave and the half-dependent branches are scalar.
+// grid (ceil(N1/W), K2, ncases), block 2*W*NB threads, dyn. LDS
+// 2*NA*(NB*W+1) complex (one transform exchange area per half, reused for the projection exchange).
+// For the projection, half h takes the entries e of parity h: in three rounds (one component
+// slot each) the halves swap the values of the entries the other half projects, so that a thread
+// holds all six components of its entries (own ones in D[r][e], the other half's in the slot D[r][e^1]
+// it has just sent), and three more rounds return the projected values.
+template <typename T, int NA, int NB, bool IDENT>
+__global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw,
+                                                             FreqTables<T> ft, GridDims g, int W, T inv_total,
+                                                             const MinresState* __restrict__ st) {
+  constexpr int N = NA * NB;
+  constexpr int TT = NB;
+  constexpr int CB = (NA + TT - 1) / TT;
+  constexpr int E0 = (NA > CB * NB) ? NA : CB * NB;
+  constexpr int E = E0 + (E0 & 1);  // even, so that every entry has a parity partner e ^ 1
+  static_assert(E <= 2 * NA, "the projection exchange must fit the two transform exchange areas");
+  extern __shared__ unsigned char smem_raw[];
+  const int cs = blockIdx.z;
+  if (st && st[cs].finish) return;
+  const int k2 = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int WNB = W * NB;  // a multiple of 64: each half is whole waves, so h is wave-uniform
+  const int q = tid % WNB, h = __builtin_amdgcn_readfirstlane(tid / WNB);
+  const int w = q % W, t = q / W;
+  const int k1 = blockIdx.x * W + w;
+  const bool ok = k1 < g.n1;
+  const int RS = NB * W + 1;
+  cx<T>* lds_all = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* lds = lds_all + h * NA * RS;
+  const long long pstride = (long long)g.n0 * g.n1;
+  cx<T>* base = spec + spec_idx(g, cs, k2, 0, 0, ok ? k1 : 0) + (long long)(3 * h) * pstride;
+
+  cx<T> D[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) D[c][i] = ok ? base[c * pstride + (long long)(t + NB * i) * g.n1] : mk<T>(0, 0);
+#pragma unroll
+    for (int i = NA; i < E; ++i) D[c][i] = mk<T>(0, 0);
+  }
+  // FP32: stage twiddles loaded once (the LDS barriers would force a reload per component); FP64
+  // reloads them from cache instead, its registers being full
+  constexpr bool HOIST = sizeof(T) == 4;
+  cx<T> twv[HOIST ? NA : 1];
+  if (HOIST) {
+#pragma unroll
+    for (int a = 1; a < NA; ++a) twv[HOIST ? a : 0] = tw[(t * a) % N];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    DFT<NA, -1, T>::run(D[c]);
+#pragma unroll
+    for (int a = 1; a < NA; ++a) D[c][a] = cmul(D[c][a], HOIST ? twv[HOIST ? a : 0] : tw[(t * a) % N]);
+    lds_barrier();
+#pragma unroll
+    for (int a = 0; a < NA; ++a) lds[a * RS + t * W + w] = D[c][a];
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) D[c][j * NB + u] = lds[a * RS + u * W + w];
+        DFT<NB, -1, T>::run(&D[c][j * NB]);
+      }
+    }
+  }
+
+  const int k1c = ok ? k1 : 0;
+  const T s1 = ft.s[1][k1c], c1 = ft.c[1][k1c], s2 = ft.s[2][k2], c2 = ft.c[2][k2];
+  const T c1c2 = c1 * c2, s1c2 = s1 * c2, c1s2 = c1 * s2;
+  if (IDENT) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int e = 0; e < E; ++e) D[c][e] = scl(D[c][e], inv_total);
+  } else {
+    // entries of one parity are numbered e / 2; the value a half hw sends for entry e of thread q
+    // sits at ((e / 2) * 2 + hw) * WNB + q (at most E * WNB <= 2 NA RS slots)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      lds_barrier();
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if ((e & 1) != h) lds_all[((e >> 1) * 2 + h) * WNB + q] = D[r][e];  // entries the other half projects
+      lds_barrier();
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if ((e & 1) == h) D[r][e ^ 1] = lds_all[((e >> 1) * 2 + (1 - h)) * WNB + q];
+    }
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int e = j * NB + b;
+          if ((e & 1) != h) continue;
+          const int k0 = a + NA * b;
+          const T s0 = ft.s[0][k0], c0 = ft.c[0][k0];
+          const T w0 = s0 * c1c2, w1 = c0 * s1c2, w2 = c0 * c1s2;
+          if (h == 0)
+            project_mandel(D[0][e], D[1][e], D[2][e], D[0][e ^ 1], D[1][e ^ 1], D[2][e ^ 1], w0, w1, w2, inv_total);
+          else
+            project_mandel(D[0][e ^ 1], D[1][e ^ 1], D[2][e ^ 1], D[0][e], D[1][e], D[2][e], w0, w1, w2, inv_total);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      lds_barrier();
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if ((e & 1) == h) lds_all[((e >> 1) * 2 + h) * WNB + q] = D[r][e ^ 1];  // the other half's, projected
+      lds_barrier();
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if ((e & 1) != h) D[r][e] = lds_all[((e >> 1) * 2 + (1 - h)) * WNB + q];
+    }
+  }
+
+  // ---- inverse along axis 0
+  cx<T> twi[HOIST ? CB : 1][HOIST ? NB : 1];
+  if (HOIST) {
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+#pragma unroll
+      for (int u = 1; u < NB; ++u) twi[HOIST ? j : 0][HOIST ? u : 0] = tw[(u * (t + TT * j)) % N];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+        DFT<NB, 1, T>::run(&D[c][j * NB]);
+        if (a > 0) {
+#pragma unroll
+          for (int u = 1; u < NB; ++u)
+            D[c][j * NB + u] = cmulc(D[c][j * NB + u], HOIST ? twi[HOIST ? j : 0][HOIST ? u : 0] : tw[(u * a) % N]);
         }
       }
     }
@@ -441,18 +625,22 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
   const T* umc = lz ? ukm1 + (long long)cs * 6 * g.nvox : nullptr;
   const T cv = lz ? (T)st[cs].cu_v : (T)0, cvp = lz ? (T)st[cs].cu_vp : (T)0;
   double acc = 0.0;
-  // all six spectrum components this thread gathers, loaded up front
+  // spectrum components this thread gathers, one pair ahead of the transform that uses them
   constexpr int LK = (N / 2 + 1 + TT - 1) / TT;
   cx<T> sp[6][LK];
+  auto gather_pair = [&](int p2) {
 #pragma unroll
-  for (int l = 0; l < LK; ++l) {
-    const int k = m + M * l;
+    for (int l = 0; l < LK; ++l) {
+      const int k = m + M * l;
 #pragma unroll
-    for (int c = 0; c < 6; ++c)
-      sp[c][l] = (n1s < g.n1 && k < g.k2) ? spec[spec_idx(g, cs, k, c, n0, n1s)] : mk<T>(0, 0);
-  }
+      for (int c = 2 * p2; c < 2 * p2 + 2; ++c)
+        sp[c][l] = (n1s < g.n1 && k < g.k2) ? spec[spec_idx(g, cs, k, c, n0, n1s)] : mk<T>(0, 0);
+    }
+  };
+  gather_pair(0);
 #pragma unroll
   for (int pr = 0; pr < 3; ++pr) {
+    if (pr < 2) gather_pair(pr + 1);
     // Lanczos operands for this pair (combination c u_k + c' u_{k-1}), fetched early
     T dv[CB][NB][2];
     if (lz && row_ok) {

@@ -411,12 +411,14 @@ static long long align_up(long long v, long long a) { return (v + a - 1) / a * a
 
 struct Tiles {
   int W1, W3, R2;  // P1/P5 row tile, P3 pencil tile, P2/P4 rows per block
+  int S3 = 2;      // P3 component split: 1 = all six per thread, 2 = three per thread (two block halves)
 };
 struct Plan {
   int n[3];
   GridDims g;
   const LenEntry* ax[3];
-  Tiles t[2];  // [0] FP32 kernels, [1] FP64 kernels
+  Tiles t[2];                   // [0] FP32 kernels, [1] FP64 kernels
+  long long lds_cap3 = 65536;   // dynamic LDS limit of the P3 kernels (the device's per-block maximum)
 };
 
 // Tuned tiles per (grid, precision), filled by rve_autotune / rve_load_tuning.
@@ -462,12 +464,21 @@ static int tile_p1(const Plan& pl, int elem) {
   while (W > 1 && 2LL * elem * W * std::max(na * (nb + 1), pl.g.n2 + 1) > kLdsCap) W /= 2;
   return W;
 }
-static int tile_p3(const Plan& pl, int elem) {
+// P3 may use the device's whole per-block LDS (160 KiB on gfx950): the split kernel's two exchange
+// areas need just over 64 KiB for 16 pencils of 256, i.e. 128-byte row segments.
+static int tile_p3_for(const Plan& pl, int elem, int sp) {
   const int na = pl.ax[0]->na, nb = pl.ax[0]->nb;
   int W = pl.t[elem == 8].W3;
-  while (W > 1 && 2LL * elem * na * (nb * W + 1) > kLdsCap) W /= 2;
+  while (W > 1 && sp * 2LL * elem * na * (nb * W + 1) > pl.lds_cap3) W /= 2;
   return W;
 }
+// The split variant needs each block half (W*NB threads) to be whole waves; otherwise whole pencils.
+static int split_p3(const Plan& pl, int elem) {
+  if (pl.t[elem == 8].S3 == 1) return 1;
+  const int W = tile_p3_for(pl, elem, 2);
+  return (W * pl.ax[0]->nb) % 64 == 0 ? 2 : 1;
+}
+static int tile_p3(const Plan& pl, int elem) { return tile_p3_for(pl, elem, split_p3(pl, elem)); }
 static int rows_p2(const Plan& pl, int elem) {
   const int na = pl.ax[1]->na, nb = pl.ax[1]->nb;
   int R = pl.t[elem == 8].R2;
@@ -493,6 +504,14 @@ static bool make_plan(const rve_grid* grid, Plan* pl) {
   g.k2 = g.n2 / 2 + 1;
   g.nvox = (long long)g.n0 * g.n1 * g.n2;
   g.spec_case = 6LL * g.k2 * g.n0 * g.n1;
+  {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+      pl->lds_cap3 = std::min<long long>(lds, 160 * 1024);
+    else
+      (void)hipGetLastError();  // no device (host-only queries): keep 64 KiB
+  }
   for (int e = 0; e < 2; ++e) {
     Tiles& t = pl->t[e];
     t.W1 = pick_tile(pl->ax[2]->nb, g.n1);
@@ -671,7 +690,8 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
   // P3
   {
     const int W = tile_p3(pl, elem);
-    const size_t lds = sizeof(cx<T>) * na0 * (nb0 * W + 1);
+    const int sp = split_p3(pl, elem);
+    const size_t lds = sizeof(cx<T>) * sp * na0 * (nb0 * W + 1);
     FreqTables<T> ft;
     for (int p = 0; p < 3; ++p) {
       ft.s[p] = tb.s[p];
@@ -679,8 +699,9 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     }
     dim3 grid((g.n1 + W - 1) / W, g.k2, nc);
     prof::begin(prof::P3, s);
-    hipLaunchKernelGGL(identity ? K0.p3_ident : K0.p3, grid, dim3(W * nb0), lds, s, spec, tb.tw[0], ft, g, W,
-                       (T)(1.0 / (double)g.nvox), st);
+    const P3Fn<T> fn = sp == 2 ? (identity ? K0.p3s_ident : K0.p3s) : (identity ? K0.p3_ident : K0.p3);
+    hipLaunchKernelGGL(fn, grid, dim3(sp * W * nb0), lds, s, spec, tb.tw[0], ft, g, W, (T)(1.0 / (double)g.nvox),
+                       st);
     prof::end(s);
   }
   // P4
@@ -964,13 +985,13 @@ int32_t rve_last_solve_info(double* initial_rel_residual, int32_t* warm_rejected
 static bool tile_fits(int threads_per_row, int W) { return W >= 1 && W * threads_per_row <= 256; }
 
 static int write_tuning_file(const char* path) {
-  // one JSON object per line: {"n":[a,b,c],"elem":e,"W1":w,"W3":w,"R2":r}
+  // one JSON object per line: {"n":[a,b,c],"elem":e,"W1":w,"W3":w,"R2":r,"S3":s}
   std::lock_guard<std::mutex> lk(g_tune_mutex);
   FILE* f = fopen(path, "w");
   if (!f) return -1;
   for (auto& e : tuned())
-    fprintf(f, "{\"n\":[%d,%d,%d],\"elem\":%d,\"W1\":%d,\"W3\":%d,\"R2\":%d}\n", e.first.n0, e.first.n1,
-            e.first.n2, e.first.elem, e.second.W1, e.second.W3, e.second.R2);
+    fprintf(f, "{\"n\":[%d,%d,%d],\"elem\":%d,\"W1\":%d,\"W3\":%d,\"R2\":%d,\"S3\":%d}\n", e.first.n0,
+            e.first.n1, e.first.n2, e.first.elem, e.second.W1, e.second.W3, e.second.R2, e.second.S3);
   fclose(f);
   return (int)tuned().size();
 }
@@ -984,10 +1005,12 @@ extern "C" int32_t rve_load_tuning(const char* path) {
   while (fgets(line, sizeof(line), f)) {
     TuneKey k;
     Tiles t;
-    if (sscanf(line, " {\"n\":[%d,%d,%d],\"elem\":%d,\"W1\":%d,\"W3\":%d,\"R2\":%d}", &k.n0, &k.n1, &k.n2,
+    if (sscanf(line, " {\"n\":[%d,%d,%d],\"elem\":%d,\"W1\":%d,\"W3\":%d,\"R2\":%d", &k.n0, &k.n1, &k.n2,
                &k.elem, &t.W1, &t.W3, &t.R2) == 7 &&
         (k.elem == 4 || k.elem == 8) && t.W1 >= 1 && t.W3 >= 1 && t.R2 >= 1 && t.W1 <= 256 && t.W3 <= 256 &&
         t.R2 <= 256) {
+      const char* sp = strstr(line, "\"S3\":");
+      t.S3 = (sp && atoi(sp + 5) == 1) ? 1 : 2;  // absent (older tables): the default
       set_tuned(k, t);
       n++;
     }
@@ -1035,6 +1058,21 @@ static rve_status autotune_impl(Plan& pl, const rve_grid* grid, int nc, const La
   double bms = 0;
   r = time_apply(&bms);
   if (r != RVE_OK) return r;
+  // P3 component split first (whole / halves), at the current tiles
+  {
+    const int keep = cur.S3;
+    cur.S3 = keep == 1 ? 2 : 1;
+    double ms = 0;
+    r = time_apply(&ms);
+    if (r != RVE_OK) {
+      cur.S3 = keep;
+      return r;
+    }
+    if (ms < bms)
+      bms = ms;
+    else
+      cur.S3 = keep;
+  }
   const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
   // coordinate descent over the three tiles (P3 pencils, P2/P4 rows, P1/P5 rows)
   for (int role = 0; role < 3; ++role) {
@@ -1094,14 +1132,15 @@ rve_status rve_autotune(const rve_grid* grid, int32_t n_cases, int32_t precision
   return RVE_OK;
 }
 
-int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles3) {
-  if (validate_grid(grid) != RVE_OK || !tiles3) return 0;
+int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles4) {
+  if (validate_grid(grid) != RVE_OK || !tiles4) return 0;
   Plan pl;
   if (!make_plan(grid, &pl)) return 0;
   const Tiles& t = pl.t[precision == RVE_FP64];
-  tiles3[0] = t.W1;
-  tiles3[1] = t.W3;
-  tiles3[2] = t.R2;
+  tiles4[0] = t.W1;
+  tiles4[1] = t.W3;
+  tiles4[2] = t.R2;
+  tiles4[3] = split_p3(pl, precision == RVE_FP64 ? 8 : 4);
   Tiles tt;
   return find_tuned(TuneKey{pl.g.n0, pl.g.n1, pl.g.n2, precision == RVE_FP64 ? 8 : 4}, &tt) ? 1 : 0;
 }
