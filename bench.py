@@ -326,8 +326,10 @@ def bench_batch(args, grids, phis, E, cfg, C1):
     rves = [(torch.as_tensor(p, device="cuda:0"), E) for p in phis]
     ws = rve.Workspace()
 
+    prec = rve.FP64 if cfg["precision"] == "fp64" else rve.FP32_MIXED
+
     def one():
-        return rve.solve_batch(rves, C1, n_streams=args.streams, tol=cfg["tol"], workspace=ws)
+        return rve.solve_batch(rves, C1, n_streams=args.streams, tol=cfg["tol"], precision=prec, workspace=ws)
 
     for i in range(args.warmup):
         out = one()
@@ -349,7 +351,8 @@ def bench_batch(args, grids, phis, E, cfg, C1):
     line = {"metric": "voxel-iterations/s + wall time to 1e-6 residual at 256^3, learned vs plain",
             "value": tot_vit / total_t, "unit": "voxel-iterations/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1e3 * total_t / args.steps, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": cfg,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == rve.FP64 else "f32", "data": "synthetic",
+            "config": cfg,
             "roofline": None, "cpu_baseline": None}
     print(json.dumps(line), flush=True)
 

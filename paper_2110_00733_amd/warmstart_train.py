@@ -13,6 +13,7 @@ solve_rve from zero with solve_rve from the network's start at larger grids.
 from __future__ import annotations
 
 import argparse
+import functools
 import json
 import math
 import os
@@ -31,9 +32,15 @@ DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart_octet64.npz")
 C_SOLID = li.isotropic_mandel(1.0, 0.3)
 
 
+@functools.lru_cache(maxsize=None)
+def _radius_range(n: int):
+    """Strut radii of the ideal octet at 3% and 30% relative density (density searches, cached)."""
+    return li.octet_radius(n, 0.03), li.octet_radius(n, 0.30)
+
+
 def sample_spec(i: int, seed0: int = 10000, n: int = 64) -> dict:
     u = li.uniforms(seed0 + i, 8)
-    r_lo, r_hi = li.octet_radius(n, 0.03), li.octet_radius(n, 0.30)
+    r_lo, r_hi = _radius_range(n)
     r = math.sqrt(r_lo ** 2 + (r_hi ** 2 - r_lo ** 2) * float(u[0]))
     return dict(radius=r, rough_amp=1.5 * float(u[1]), rough_sigma=1.0 + 2.0 * float(u[2]),
                 n_pores=min(int(9 * float(u[3])), 8), pore_median_vox=1.0 + float(u[4]),
