@@ -812,6 +812,8 @@ static std::vector<unsigned char> chunk_key(const Plan& pl, int nc, const Minres
     k.insert(k.end(), c, c + n);
   };
   put(pl.n, sizeof(pl.n));
+  put(pl.t, sizeof(pl.t));  // tiles and splits: a retune or a loaded table recaptures
+  put(&pl.lds_cap3, sizeof(pl.lds_cap3));
   put(&nc, sizeof(nc));
   put(&B, sizeof(B));
   put(&phi, sizeof(phi));
