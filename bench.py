@@ -85,7 +85,7 @@ def algorithmic_bytes(kind, n, nc, elem):
 KIND_TO_KERNEL = {  # profiler kind -> rocprofv3 kernel name prefix (FP32 fields)
     "P1_stiffness_fft_axis2_alpha": "rve::k_fwd_axis2<{t},",
     "P2_fft_axis1": "rve::k_axis1<{t},*,-1>",
-    "P3_fft_axis0_projection": "rve::k_axis0_project<{t},",
+    "P3_fft_axis0_projection": "rve::k_axis0_project_split<{t},",  # the variant the tuner keeps at 256^3
     "P4_ifft_axis1": "rve::k_axis1<{t},*,1>",
     "P5_ifft_axis2_lanczos": "rve::k_inv_axis2<{t},",
     "U2_direction_update": "rve::k_direction<{t},",
