@@ -77,7 +77,8 @@ def algorithmic_bytes(kind, n, nc, elem):
         "P3_fft_axis0_projection": 2 * spec,
         "P4_ifft_axis1": 2 * spec,
         "P5_ifft_axis2_lanczos": spec + 3 * field,        # spectrum, u_k, u_k-1 -> u_k+1
-        "U2_direction_update": 6 * field,                        # u_k, d_k-1, d_k-2, x -> d_k, x
+        # u_k, d_k-1, d_k-2 -> d_k every iteration; x read and written every second one (5 fields on average)
+        "U2_direction_update": 5 * field,
     }
     return table.get(kind, 0) * nc
 

@@ -36,9 +36,29 @@ struct MinresState {
   double tol_abs;                    // stop when |phibar| <= tol_abs
   double cu_v, cu_vp;                // Lanczos update coefficients (on raw u_k, u_{k-1})
   double cd_u, cd_d1, cd_d2, cx;     // search-direction / solution update coefficients
+  double cx_prev;                    // solution coefficient of the previous direction when deferred
   double sumsq;                      // scratch: last reduced sum
-  int iter, max_iter, finish, done, status, pad;
+  int iter, max_iter, finish, done, status;
+  int xmode;    // U2's solution update: 0 defer, 1 x += cx d_k, 2 x += cx_prev d_{k-1} + cx d_k
+  int pending;  // a deferred cx_prev d_{k-1} is owed to x
+  int pad;
 };
+
+// U2 touches x only every second iteration: the update of an even iteration is deferred and added
+// together with the next one (d_{k-1} is still in its buffer then), and a finishing iteration
+// always settles what is owed.
+__device__ __forceinline__ void schedule_x_update(MinresState& S) {
+  if (S.pending) {
+    S.xmode = 2;
+    S.pending = 0;
+  } else if (S.finish) {
+    S.xmode = 1;
+  } else {
+    S.xmode = 0;
+    S.pending = 1;
+    S.cx_prev = S.cx;
+  }
+}
 
 template <typename T>
 struct Material {
@@ -92,12 +112,14 @@ __device__ __forceinline__ void givens_step(MinresState& S, double sumsq) {
     S.status = -3;  // non-finite scalar
     S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = 0.0;
     S.finish = 1;
+    schedule_x_update(S);
     return;
   }
   if (gamma == 0.0) {
     S.status = 2;  // breakdown
     S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = 0.0;
     S.finish = 1;
+    schedule_x_update(S);
     return;
   }
   const double c = gtil / gamma, sn = beta_next / gamma;
@@ -120,6 +142,7 @@ __device__ __forceinline__ void givens_step(MinresState& S, double sumsq) {
     S.status = 1;  // not converged
     S.finish = 1;
   }
+  schedule_x_update(S);
 }
 
 // ============================================================================ P1

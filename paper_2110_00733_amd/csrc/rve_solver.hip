@@ -228,7 +228,9 @@ __global__ void k_minres_init(MinresState* st, const double* partials, int np, C
     S.s1 = S.s2 = 0.0;
     S.phibar = beta;
     S.tol_abs = fmax(safety * tol * ci[cs].bnorm, inner_floor * beta);
-    S.cu_v = S.cu_vp = S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = 0.0;
+    S.cu_v = S.cu_vp = S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = S.cx_prev = 0.0;
+    S.xmode = 0;
+    S.pending = 0;
     S.iter = 0;
     S.max_iter = max_iter - ci[cs].iters;
     S.status = 0;
@@ -285,7 +287,8 @@ __global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* 
   const int cs = blockIdx.y;
   const MinresState& S = st[cs];
   if (S.done) return;
-  const T a = (T)S.cd_u, b = (T)S.cd_d1, c = (T)S.cd_d2, xc = (T)S.cx;
+  const T a = (T)S.cd_u, b = (T)S.cd_d1, c = (T)S.cd_d2, xc = (T)S.cx, xp = (T)S.cx_prev;
+  const int mode = S.xmode;  // uniform per block (one case)
   const long long off = (long long)cs * n6;
   constexpr int V = VEC ? Vec16<T>::n : 1;
   using VT = typename Vec16<T>::type;
@@ -293,25 +296,26 @@ __global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* 
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
     if constexpr (VEC) {
       VT dv = reinterpret_cast<const VT*>(d2 + off)[i];
-      VT xv = reinterpret_cast<const VT*>(x + off)[i];
       const VT uv = reinterpret_cast<const VT*>(uk + off)[i];
       const VT d1v = reinterpret_cast<const VT*>(d1 + off)[i];
       T* de = reinterpret_cast<T*>(&dv);
-      T* xe = reinterpret_cast<T*>(&xv);
       const T* ue = reinterpret_cast<const T*>(&uv);
       const T* d1e = reinterpret_cast<const T*>(&d1v);
 #pragma unroll
-      for (int e = 0; e < V; ++e) {
-        const T d = a * ue[e] + b * d1e[e] + c * de[e];
-        de[e] = d;
-        xe[e] += xc * d;
-      }
+      for (int e = 0; e < V; ++e) de[e] = a * ue[e] + b * d1e[e] + c * de[e];
       reinterpret_cast<VT*>(d2 + off)[i] = dv;
-      reinterpret_cast<VT*>(x + off)[i] = xv;
+      if (mode != 0) {
+        VT xv = reinterpret_cast<const VT*>(x + off)[i];
+        T* xe = reinterpret_cast<T*>(&xv);
+#pragma unroll
+        for (int e = 0; e < V; ++e) xe[e] += (mode == 2 ? xp * d1e[e] : (T)0) + xc * de[e];
+        reinterpret_cast<VT*>(x + off)[i] = xv;
+      }
     } else {
-      const T d = a * uk[off + i] + b * d1[off + i] + c * d2[off + i];
+      const T d1s = d1[off + i];
+      const T d = a * uk[off + i] + b * d1s + c * d2[off + i];
       d2[off + i] = d;
-      x[off + i] += xc * d;
+      if (mode != 0) x[off + i] += (mode == 2 ? xp * d1s : (T)0) + xc * d;
     }
   }
 }
