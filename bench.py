@@ -326,6 +326,13 @@ def bench_batch(args, grids, phis, E, cfg, C1):
     import paper_2110_00733_amd as rve
     rves = [(torch.as_tensor(p, device="cuda:0"), E) for p in phis]
     ws = rve.Workspace()
+    if not args.no_autotune:
+        ta = time.time()
+        prec_t = rve.FP64 if cfg["precision"] == "fp64" else rve.FP32_MIXED
+        for g in sorted(set(grids)):
+            rve.autotune(g, n_cases=E.shape[0], precision=prec_t, workspace=ws)
+        cfg["autotuned_grids"] = len(set(grids))
+        log(f"autotuned {len(set(grids))} grids in {time.time() - ta:.1f}s")
 
     prec = rve.FP64 if cfg["precision"] == "fp64" else rve.FP32_MIXED
 

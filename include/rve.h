@@ -168,7 +168,8 @@ void rve_profile_reset(void);
 int32_t rve_profile_read(double* total_ms, int64_t* launches, int32_t max_kinds);
 const char* rve_profile_kind_name(int32_t kind);
 
-/* Autotuner.  Times the operator apply for the P3 component split (whole / halves) and every
+/* Autotuner.  Times the operator apply for each registered factorisation N = NA * NB of every axis
+ * length (e.g. 64 = 8*8 or 16*4, 96 = 12*8 or 16*6), the P3 component split (whole / halves) and every
  * admissible tile width of each pass kind (P3 pencils per block, P2/P4 rows per block, P1/P5 rows
  * per block; coordinate descent, HIP events on
  * hip_stream, 3 repetitions each) for this grid and precision, using the caller's workspace (at least
@@ -183,11 +184,12 @@ rve_status rve_autotune(const rve_grid* grid, int32_t n_cases, int32_t precision
  * plans a grid).  Returns the number of entries loaded, -1 if the file cannot be read. */
 int32_t rve_load_tuning(const char* path);
 
-/* Tiles the next call on this grid and precision will use: tiles4 = {P1/P5 rows, P3 pencils,
+/* Tiles the next call on this grid and precision will use: tiles7 = {P1/P5 rows, P3 pencils,
  * P2/P4 rows, P3 component split in effect (1: six components per thread, 2: three per thread over
- * two block halves; the split needs each half to be whole 64-lane waves)}.  Returns 1 if they come
- * from the tuner, 0 if they are the built-in heuristic. */
-int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles4);
+ * two block halves; the split needs each half to be whole 64-lane waves), then for axes 0, 1, 2 the
+ * first-stage radix NA of the factorisation N = NA * NB in use}.  Returns 1 if they come from the
+ * tuner, 0 if they are the built-in heuristic. */
+int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles7);
 
 /* Text of the last HIP runtime failure behind an RVE_EDEVICE in this thread ("" if none). */
 const char* rve_last_error(void);

@@ -154,9 +154,9 @@ def autotune(n, n_cases: int = 1, precision: int = FP32_MIXED, cache_path: str |
 
 
 def tuned_tiles(n, precision: int = FP32_MIXED, L=(1.0, 1.0, 1.0)):
-    """((P1/P5 rows, P3 pencils, P2/P4 rows, P3 component split), from_tuner)"""
+    """((P1/P5 rows, P3 pencils, P2/P4 rows, P3 component split, NA axis 0, NA axis 1, NA axis 2), from_tuner)"""
     g = make_grid(n, L)
-    t = (ctypes.c_int32 * 4)()
+    t = (ctypes.c_int32 * 7)()
     f = load_library().rve_tuned_tiles(ctypes.byref(g), int(precision), t)
     return tuple(t), bool(f)
 

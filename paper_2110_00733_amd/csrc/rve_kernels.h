@@ -66,7 +66,21 @@ struct Material {
   T Cd[36];  // C_solid - C_void:  C(x) = C0 + phi(x) Cd  (Voigt rule)
   int has_c0;
   int use_phi;  // 0: C(x) = C0 everywhere (phi is not read)
+  // isotropic fast path (set when the Mandel matrix is exactly lam 1(x)1 + mu2 I):
+  // sigma = lam tr(eps) 1 + mu2 eps, with 1 = (1,1,1,0,0,0)
+  int iso_d, iso_0;
+  T lam_d, mu2_d, lam_0, mu2_0;
 };
+
+// sigma_a = (C e)_a for one voxel, general 6x6 or isotropic form
+template <typename T>
+__device__ __forceinline__ T stiff_row(const T* C, int iso, T lam, T mu2, int a, const T (&e)[6], T tr) {
+  if (iso) return (a < 3 ? lam * tr : (T)0) + mu2 * e[a];
+  T sv = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) sv += C[a * 6 + b] * e[b];
+  return sv;
+}
 
 template <typename T>
 struct FreqTables {
@@ -184,18 +198,15 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
     // element by element, so that e[.][i] is dead once sg[.][i] and its <x, sigma> terms exist
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
+      T ev[6];
+#pragma unroll
+      for (int b = 0; b < 6; ++b) ev[b] = e[b][i];
+      const T tr = ev[0] + ev[1] + ev[2];
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
         T sv = 0;
-        if (mat.use_phi) {
-#pragma unroll
-          for (int b = 0; b < 6; ++b) sv += mat.Cd[a * 6 + b] * e[b][i];
-          sv *= ph[i];
-        }
-        if (mat.has_c0) {
-#pragma unroll
-          for (int b = 0; b < 6; ++b) sv += mat.C0[a * 6 + b] * e[b][i];
-        }
+        if (mat.use_phi) sv = ph[i] * stiff_row(mat.Cd, mat.iso_d, mat.lam_d, mat.mu2_d, a, ev, tr);
+        if (mat.has_c0) sv += stiff_row(mat.C0, mat.iso_0, mat.lam_0, mat.mu2_0, a, ev, tr);
         sg[a][i] = sv * xs;
       }
       if (partials) {

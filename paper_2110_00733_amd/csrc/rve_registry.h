@@ -37,7 +37,7 @@ template <>
 inline const LenKernels<double>& LenEntry::k<double>() const { return d; }
 
 void register_len(const LenEntry& e);
-const LenEntry* find_len(int n);
+const LenEntry* find_len(int n, int variant = 0);
 
 }  // namespace rve
 

@@ -32,10 +32,16 @@ static std::vector<LenEntry>& registry() {
   return r;
 }
 void register_len(const LenEntry& e) { registry().push_back(e); }
-const LenEntry* find_len(int n) {
+// The v-th registered factorisation of length n (v = 0: the default, the first registered).
+const LenEntry* find_len(int n, int v) {
   for (const auto& e : registry())
-    if (e.n == n) return &e;
+    if (e.n == n && v-- == 0) return &e;
   return nullptr;
+}
+static int len_variants(int n) {
+  int k = 0;
+  for (const auto& e : registry()) k += e.n == n;
+  return k;
 }
 void register_group_a();
 void register_group_b();
@@ -414,16 +420,18 @@ __global__ void k_check_phi(const float* phi, long long n, int* bad) {
 static long long align_up(long long v, long long a) { return (v + a - 1) / a * a; }
 
 struct Tiles {
-  int W1, W3, R2;  // P1/P5 row tile, P3 pencil tile, P2/P4 rows per block
-  int S3 = 2;      // P3 component split: 1 = all six per thread, 2 = three per thread (two block halves)
+  int W1, W3, R2;       // P1/P5 row tile, P3 pencil tile, P2/P4 rows per block
+  int S3 = 2;           // P3 component split: 1 = all six per thread, 2 = three per thread (two block halves)
+  int F[3] = {0, 0, 0};  // factorisation (registry variant) of each axis length
 };
 struct Plan {
   int n[3];
   GridDims g;
-  const LenEntry* ax[3];
+  const LenEntry* ax[2][3];     // per precision ([0] FP32, [1] FP64) and axis: the kernels in use
   Tiles t[2];                   // [0] FP32 kernels, [1] FP64 kernels
   long long lds_cap3 = 65536;   // dynamic LDS limit of the P3 kernels (the device's per-block maximum)
 };
+static const LenEntry* axis(const Plan& pl, int elem, int p) { return pl.ax[elem == 8][p]; }
 
 // Tuned tiles per (grid, precision), filled by rve_autotune / rve_load_tuning.
 struct TuneKey {
@@ -460,46 +468,56 @@ static int pick_tile(int threads_per_row, int len) {
   return W;
 }
 
-// Largest tile not above the plan's choice whose dynamic LDS stays within 64 KiB.
+// Largest tile not above the plan's choice with at most 256 threads per block (per half for the
+// split P3) and dynamic LDS within 64 KiB (P1/P5, P2/P4) or the device limit (P3).
 constexpr long long kLdsCap = 64 * 1024;
 static int tile_p1(const Plan& pl, int elem) {
-  const int na = pl.ax[2]->na, nb = pl.ax[2]->nb;
+  const int na = axis(pl, elem, 2)->na, nb = axis(pl, elem, 2)->nb;
   int W = pl.t[elem == 8].W1;
-  while (W > 1 && 2LL * elem * W * std::max(na * (nb + 1), pl.g.n2 + 1) > kLdsCap) W /= 2;
+  while (W > 1 && (W * nb > 256 || 2LL * elem * W * std::max(na * (nb + 1), pl.g.n2 + 1) > kLdsCap)) W /= 2;
   return W;
 }
 // P3 may use the device's whole per-block LDS (160 KiB on gfx950): the split kernel's two exchange
 // areas need just over 64 KiB for 16 pencils of 256, i.e. 128-byte row segments.
 static int tile_p3_for(const Plan& pl, int elem, int sp) {
-  const int na = pl.ax[0]->na, nb = pl.ax[0]->nb;
+  const int na = axis(pl, elem, 0)->na, nb = axis(pl, elem, 0)->nb;
   int W = pl.t[elem == 8].W3;
-  while (W > 1 && sp * 2LL * elem * na * (nb * W + 1) > pl.lds_cap3) W /= 2;
+  while (W > 1 && (W * nb > 256 || sp * 2LL * elem * na * (nb * W + 1) > pl.lds_cap3)) W /= 2;
   return W;
 }
 // The split variant needs each block half (W*NB threads) to be whole waves; otherwise whole pencils.
 static int split_p3(const Plan& pl, int elem) {
   if (pl.t[elem == 8].S3 == 1) return 1;
   const int W = tile_p3_for(pl, elem, 2);
-  return (W * pl.ax[0]->nb) % 64 == 0 ? 2 : 1;
+  return (W * axis(pl, elem, 0)->nb) % 64 == 0 ? 2 : 1;
 }
 static int tile_p3(const Plan& pl, int elem) { return tile_p3_for(pl, elem, split_p3(pl, elem)); }
 static int rows_p2(const Plan& pl, int elem) {
-  const int na = pl.ax[1]->na, nb = pl.ax[1]->nb;
+  const int na = axis(pl, elem, 1)->na, nb = axis(pl, elem, 1)->nb;
   int R = pl.t[elem == 8].R2;
-  while (R > 1 && 2LL * elem * R * na * (nb + 1) > kLdsCap) R /= 2;
+  while (R > 1 && (R * nb > 256 || 2LL * elem * R * na * (nb + 1) > kLdsCap)) R /= 2;
   return R;
 }
-static int partials_p5(const Plan& pl, int elem) {
-  const int W = tile_p1(pl, elem);
-  return pl.g.n0 * ((pl.g.n1 + W - 1) / W);
+
+// Kernel entries of every axis for each precision from the tiles' factorisation choice (an unknown
+// variant falls back to the default).
+static void select_axes(Plan* pl) {
+  for (int e = 0; e < 2; ++e)
+    for (int p = 0; p < 3; ++p) {
+      const LenEntry* a = find_len(pl->n[p], pl->t[e].F[p]);
+      if (!a) {
+        pl->t[e].F[p] = 0;
+        a = find_len(pl->n[p], 0);
+      }
+      pl->ax[e][p] = a;
+    }
 }
 
 static bool make_plan(const rve_grid* grid, Plan* pl) {
   ensure_registry();
   for (int p = 0; p < 3; ++p) {
     pl->n[p] = grid->n[p];
-    pl->ax[p] = find_len(grid->n[p]);
-    if (!pl->ax[p]) return false;
+    if (!find_len(grid->n[p])) return false;
   }
   GridDims& g = pl->g;
   g.n0 = pl->n[0];
@@ -518,12 +536,16 @@ static bool make_plan(const rve_grid* grid, Plan* pl) {
   }
   for (int e = 0; e < 2; ++e) {
     Tiles& t = pl->t[e];
-    t.W1 = pick_tile(pl->ax[2]->nb, g.n1);
-    t.W3 = pick_tile(pl->ax[0]->nb, g.n1);
-    t.R2 = std::max(1, std::min(64, 256 / pl->ax[1]->nb));
+    const LenEntry* a0 = find_len(pl->n[0]);
+    const LenEntry* a1 = find_len(pl->n[1]);
+    const LenEntry* a2 = find_len(pl->n[2]);
+    t.W1 = pick_tile(a2->nb, g.n1);
+    t.W3 = pick_tile(a0->nb, g.n1);
+    t.R2 = std::max(1, std::min(64, 256 / a1->nb));
     Tiles tt;
     if (find_tuned(TuneKey{g.n0, g.n1, g.n2, e ? 8 : 4}, &tt)) t = tt;
   }
+  select_axes(pl);
   return true;
 }
 
@@ -635,17 +657,45 @@ static rve_status build_tables(const Plan& pl, const rve_grid* grid, char* base,
   return RVE_OK;
 }
 
+// Exactly isotropic Mandel stiffness lam 1(x)1 + mu2 I (lam = C01, mu2 = C33, bitwise): the P1 fast path.
+static bool isotropic_form(const double* C, double* lam, double* mu2) {
+  *lam = C[1];
+  *mu2 = C[21];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      double want = 0.0;
+      if (i < 3 && j < 3) want = (i == j) ? *lam + *mu2 : *lam;
+      else if (i == j) want = *mu2;
+      if (C[i * 6 + j] != want) return false;
+    }
+  return true;
+}
+
 template <typename T>
 static Material<T> make_material(const double* Cvoid, const double* Csolid) {
   Material<T> m;
+  memset(&m, 0, sizeof(m));
   bool any = false;
+  double Cd[36];
   for (int i = 0; i < 36; ++i) {
     m.C0[i] = (T)Cvoid[i];
-    m.Cd[i] = (T)(Csolid[i] - Cvoid[i]);
+    Cd[i] = Csolid[i] - Cvoid[i];
+    m.Cd[i] = (T)Cd[i];
     any = any || Cvoid[i] != 0.0;
   }
   m.has_c0 = any ? 1 : 0;
   m.use_phi = 1;
+  double lam, mu2;
+  if (isotropic_form(Cd, &lam, &mu2)) {
+    m.iso_d = 1;
+    m.lam_d = (T)lam;
+    m.mu2_d = (T)mu2;
+  }
+  if (isotropic_form(Cvoid, &lam, &mu2)) {
+    m.iso_0 = 1;
+    m.lam_0 = (T)lam;
+    m.mu2_0 = (T)mu2;
+  }
   return m;
 }
 
@@ -658,12 +708,13 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
                      const Material<T>& mat, const Tables<T>& tb, cx<T>* spec, T* y, const T* uk, const T* ukm1,
                      double* partials, MinresState* st, int identity, hipStream_t s) {
   const GridDims& g = pl.g;
-  const LenKernels<T>& K0 = pl.ax[0]->k<T>();
-  const LenKernels<T>& K1 = pl.ax[1]->k<T>();
-  const LenKernels<T>& K2 = pl.ax[2]->k<T>();
-  const int na2 = pl.ax[2]->na, nb2 = pl.ax[2]->nb;
-  const int na1 = pl.ax[1]->na, nb1 = pl.ax[1]->nb;
-  const int na0 = pl.ax[0]->na, nb0 = pl.ax[0]->nb;
+  constexpr int el = (int)sizeof(T);
+  const LenKernels<T>& K0 = axis(pl, el, 0)->k<T>();
+  const LenKernels<T>& K1 = axis(pl, el, 1)->k<T>();
+  const LenKernels<T>& K2 = axis(pl, el, 2)->k<T>();
+  const int na2 = axis(pl, el, 2)->na, nb2 = axis(pl, el, 2)->nb;
+  const int na1 = axis(pl, el, 1)->na, nb1 = axis(pl, el, 1)->nb;
+  const int na0 = axis(pl, el, 0)->na, nb0 = axis(pl, el, 0)->nb;
   const int N2 = g.n2;
   const int elem = (int)sizeof(T);
   // P1
@@ -991,13 +1042,14 @@ int32_t rve_last_solve_info(double* initial_rel_residual, int32_t* warm_rejected
 static bool tile_fits(int threads_per_row, int W) { return W >= 1 && W * threads_per_row <= 256; }
 
 static int write_tuning_file(const char* path) {
-  // one JSON object per line: {"n":[a,b,c],"elem":e,"W1":w,"W3":w,"R2":r,"S3":s}
+  // one JSON object per line: {"n":[a,b,c],"elem":e,"W1":w,"W3":w,"R2":r,"S3":s,"F":[f0,f1,f2]}
   std::lock_guard<std::mutex> lk(g_tune_mutex);
   FILE* f = fopen(path, "w");
   if (!f) return -1;
   for (auto& e : tuned())
-    fprintf(f, "{\"n\":[%d,%d,%d],\"elem\":%d,\"W1\":%d,\"W3\":%d,\"R2\":%d,\"S3\":%d}\n", e.first.n0,
-            e.first.n1, e.first.n2, e.first.elem, e.second.W1, e.second.W3, e.second.R2, e.second.S3);
+    fprintf(f, "{\"n\":[%d,%d,%d],\"elem\":%d,\"W1\":%d,\"W3\":%d,\"R2\":%d,\"S3\":%d,\"F\":[%d,%d,%d]}\n",
+            e.first.n0, e.first.n1, e.first.n2, e.first.elem, e.second.W1, e.second.W3, e.second.R2, e.second.S3,
+            e.second.F[0], e.second.F[1], e.second.F[2]);
   fclose(f);
   return (int)tuned().size();
 }
@@ -1017,6 +1069,14 @@ extern "C" int32_t rve_load_tuning(const char* path) {
         t.R2 <= 256) {
       const char* sp = strstr(line, "\"S3\":");
       t.S3 = (sp && atoi(sp + 5) == 1) ? 1 : 2;  // absent (older tables): the default
+      const char* fp = strstr(line, "\"F\":[");
+      int f0 = 0, f1 = 0, f2 = 0;
+      if (fp && sscanf(fp, "\"F\":[%d,%d,%d]", &f0, &f1, &f2) == 3 && f0 >= 0 && f1 >= 0 && f2 >= 0 && f0 < 16 &&
+          f1 < 16 && f2 < 16) {
+        t.F[0] = f0;
+        t.F[1] = f1;
+        t.F[2] = f2;
+      }
       set_tuned(k, t);
       n++;
     }
@@ -1064,7 +1124,32 @@ static rve_status autotune_impl(Plan& pl, const rve_grid* grid, int nc, const La
   double bms = 0;
   r = time_apply(&bms);
   if (r != RVE_OK) return r;
-  // P3 component split first (whole / halves), at the current tiles
+  // factorisation of each axis length first (tiles are clamped to what each one allows)
+  for (int p = 0; p < 3; ++p) {
+    const int nv = len_variants(pl.n[p]);
+    if (nv < 2) continue;
+    const int keep = cur.F[p];
+    int bestv = keep;
+    for (int v = 0; v < nv; ++v) {
+      if (v == keep) continue;
+      cur.F[p] = v;
+      select_axes(&pl);
+      double ms = 0;
+      r = time_apply(&ms);
+      if (r != RVE_OK) {
+        cur.F[p] = keep;
+        select_axes(&pl);
+        return r;
+      }
+      if (ms < bms) {
+        bms = ms;
+        bestv = v;
+      }
+    }
+    cur.F[p] = bestv;
+    select_axes(&pl);
+  }
+  // P3 component split (whole / halves), at the current tiles
   {
     const int keep = cur.S3;
     cur.S3 = keep == 1 ? 2 : 1;
@@ -1082,7 +1167,7 @@ static rve_status autotune_impl(Plan& pl, const rve_grid* grid, int nc, const La
   const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
   // coordinate descent over the three tiles (P3 pencils, P2/P4 rows, P1/P5 rows)
   for (int role = 0; role < 3; ++role) {
-    const int nb = role == 0 ? pl.ax[0]->nb : role == 1 ? pl.ax[1]->nb : pl.ax[2]->nb;
+    const int nb = axis(pl, elem, role == 0 ? 0 : role == 1 ? 1 : 2)->nb;
     int* slot = role == 0 ? &cur.W3 : role == 1 ? &cur.R2 : &cur.W1;
     const int keep = *slot;
     int bestv = keep;
@@ -1138,15 +1223,17 @@ rve_status rve_autotune(const rve_grid* grid, int32_t n_cases, int32_t precision
   return RVE_OK;
 }
 
-int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles4) {
-  if (validate_grid(grid) != RVE_OK || !tiles4) return 0;
+int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles7) {
+  if (validate_grid(grid) != RVE_OK || !tiles7) return 0;
   Plan pl;
   if (!make_plan(grid, &pl)) return 0;
-  const Tiles& t = pl.t[precision == RVE_FP64];
-  tiles4[0] = t.W1;
-  tiles4[1] = t.W3;
-  tiles4[2] = t.R2;
-  tiles4[3] = split_p3(pl, precision == RVE_FP64 ? 8 : 4);
+  const int elem = precision == RVE_FP64 ? 8 : 4;
+  const Tiles& t = pl.t[elem == 8];
+  tiles7[0] = t.W1;
+  tiles7[1] = t.W3;
+  tiles7[2] = t.R2;
+  tiles7[3] = split_p3(pl, elem);
+  for (int p = 0; p < 3; ++p) tiles7[4 + p] = axis(pl, elem, p)->na;
   Tiles tt;
   return find_tuned(TuneKey{pl.g.n0, pl.g.n1, pl.g.n2, precision == RVE_FP64 ? 8 : 4}, &tt) ? 1 : 0;
 }
