@@ -218,31 +218,43 @@ def main():
     rve.profile_reset()
     rve.profile_enable(True)
     tp = time.perf_counter()
+    prof_iters = 0
     for i in range(args.profile_steps):
         out = one()
+        prof_iters += int(out["iterations"].sum())
     torch.cuda.synchronize()
     log(f"profiled steps: {1e3 * (time.perf_counter() - tp) / max(args.profile_steps, 1):.1f} ms per solve")
     rve.profile_enable(False)
     prof = rve.profile_read()
 
     # roofline entry for the kernel with the largest share of the timed loop
+    # Kinds of the solve's own precision run once per MINRES iteration; a launch of a chunk's iterations
+    # after convergence returns at once, so the time of a working launch is the kind's total over the
+    # iteration count (per case when the cases share a launch).  The other precision's kinds are the
+    # FP64 residual applies of the FP32-mixed solver, every launch of which works.
     elem = 8 if prec == rve.FP64 else 4
     kernels = {}
     for k, (ms, cnt) in prof.items():
         if cnt == 0:
             continue
-        avg = ms / cnt
-        ab = algorithmic_bytes(k, n, nc, elem)
-        kernels[k] = {"total_ms": ms, "launches": cnt, "avg_us": 1e3 * avg, "alg_bytes": ab,
-                      "gbs": (ab / (avg * 1e-3) / 1e9) if ab else None}
-    dom = max(kernels, key=lambda k: kernels[k]["total_ms"]) if kernels else None
+        is64 = k.endswith("_f64")
+        own = is64 == (elem == 8)
+        work = prof_iters / nc if own else cnt
+        if work <= 0:
+            continue
+        avg = ms / work
+        ab = algorithmic_bytes(k[:-4] if is64 else k, n, nc, 8 if is64 else 4)
+        kernels[k] = {"total_ms": ms, "launches": cnt, "working_launches": round(work, 1), "avg_us": 1e3 * avg,
+                      "alg_bytes": ab, "gbs": (ab / (avg * 1e-3) / 1e9) if ab else None}
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"] if kernels[k]["alg_bytes"] else 0) if kernels else None
     roof = None
     if dom:
         kd = kernels[dom]
         ach = kd["gbs"] or 0.0
-        traffic = measured_traffic(cfg["workload"], dom, "double" if prec == rve.FP64 else "float")
+        traffic = measured_traffic(cfg["workload"], dom.removesuffix("_f64"), "double" if prec == rve.FP64 else "float")
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "avg_us": round(kd["avg_us"], 2),
+                "launches": kd["launches"], "working_launches": kd["working_launches"],
                 "alg_bytes_per_launch": kd["alg_bytes"]}
     log(json.dumps({k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()}))

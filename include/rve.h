@@ -73,11 +73,13 @@ typedef struct {
                            own starting residual (default 3e-2; in (0, 1)).  FP32 Lanczos on these
                            near-singular operators stalls when asked for much deeper reductions; the
                            FP64 refinement restarts from the true residual instead */
-  double inner_safety;  /* FP32_MIXED: an inner sweep aims at inner_safety * tol * ||b|| (default 0.5) */
+  double inner_safety;  /* FP32_MIXED: an inner sweep aims at inner_safety * tol * ||b|| (default 0.9; the
+                           FP64 residual decides, so a sweep that ends just above tol is followed by
+                           another one) */
 } rve_options;
 
 /* Fills *opt with the defaults: tol 1e-6, max_iter 5000, FP32_MIXED, max_refine 24, natural Nyquist,
- * rotated scheme, check_every 24, inner_floor 3e-2, inner_safety 0.5. */
+ * rotated scheme, check_every 24, inner_floor 3e-2, inner_safety 0.9. */
 void rve_default_options(rve_options* opt);
 
 /* 1 if the FFT kernels provide axis length n (n = NA*NB with radix factors 2, 3, 4, 5), else 0. */
@@ -159,10 +161,14 @@ rve_status rve_apply(const rve_grid* grid, const float* voxel_fraction_field, co
  * recorded on the solve stream; elapsed times are accumulated per kernel kind at the host's
  * convergence checks.  Kinds, in order: P1 stiffness + FFT axis 2 (+ Lanczos alpha), P2 FFT axis 1,
  * P3 FFT axis 0 + projection + inverse, P4 inverse FFT axis 1, P5 inverse FFT axis 2 + Lanczos
- * update, S1 Lanczos alpha, S2 Givens step, U2 direction + solution update.
+ * update, S1 Lanczos alpha, S2 Givens step, U2 direction + solution update; kinds 0-7 count these
+ * passes on FP32 fields, kinds 8-15 (names ending in _f64) the same passes on FP64 fields.
  * rve_profile_read fills total milliseconds and launch counts for up to max_kinds kinds and
- * returns the number of kinds.  Profiled solves launch their kernels directly (no graph replay), so
- * each launch can be bracketed; kernel durations do not depend on the launch path. */
+ * returns the number of kinds (16).  Profiled solves launch their kernels directly (no graph
+ * replay), so each launch can be bracketed; kernel durations do not depend on the launch path.
+ * Launch counts include the iterations of the last launched chunk after convergence, whose kernels
+ * return at once (a few microseconds each); divide by the iteration count for the time of a
+ * working launch. */
 void rve_profile_enable(int32_t on);
 void rve_profile_reset(void);
 int32_t rve_profile_read(double* total_ms, int64_t* launches, int32_t max_kinds);

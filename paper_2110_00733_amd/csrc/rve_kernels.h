@@ -367,7 +367,9 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int cs = blockIdx.z;
   if (st && st[cs].finish) return;
-  const int k2 = blockIdx.y;
+  // planes in descending k2: P2 (ascending rows) wrote the high planes last, so part of them is still in
+  // the memory-side cache, and P4 (ascending again) then starts on the planes written last here
+  const int k2 = g.k2 - 1 - (int)blockIdx.y;
   const int tid = threadIdx.x;
   const int w = tid % W, t = tid / W;
   const int k1 = blockIdx.x * W + w;
@@ -483,7 +485,9 @@ __global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__
   extern __shared__ unsigned char smem_raw[];
   const int cs = blockIdx.z;
   if (st && st[cs].finish) return;
-  const int k2 = blockIdx.y;
+  // planes in descending k2: P2 (ascending rows) wrote the high planes last, so part of them is still in
+  // the memory-side cache, and P4 (ascending again) then starts on the planes written last here
+  const int k2 = g.k2 - 1 - (int)blockIdx.y;
   const int tid = threadIdx.x;
   const int WNB = W * NB;  // a multiple of 64: each half is whole waves, so h is wave-uniform
   const int q = tid % WNB, h = __builtin_amdgcn_readfirstlane(tid / WNB);

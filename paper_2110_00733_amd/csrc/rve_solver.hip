@@ -63,20 +63,27 @@ static void ensure_registry() {
 // Events come from a pool created on first enable; pairs are read back at the host's chunk syncs.
 namespace prof {
 enum Kind { P1 = 0, P2, P3, P4, P5, S1, S2, U2, NKIND };
-static const char* kNames[NKIND] = {"P1_stiffness_fft_axis2_alpha", "P2_fft_axis1", "P3_fft_axis0_projection",
-                                    "P4_ifft_axis1", "P5_ifft_axis2_lanczos", "S1_alpha", "S2_givens",
-                                    "U2_direction_update"};
+// kinds 0..NKIND-1 time passes on FP32 fields, NKIND..2 NKIND-1 the same passes on FP64 fields
+constexpr int NSLOT = 2 * NKIND;
+static const char* kNames[NSLOT] = {
+    "P1_stiffness_fft_axis2_alpha",     "P2_fft_axis1",     "P3_fft_axis0_projection",
+    "P4_ifft_axis1",                    "P5_ifft_axis2_lanczos", "S1_alpha", "S2_givens", "U2_direction_update",
+    "P1_stiffness_fft_axis2_alpha_f64", "P2_fft_axis1_f64", "P3_fft_axis0_projection_f64",
+    "P4_ifft_axis1_f64",                "P5_ifft_axis2_lanczos_f64", "S1_alpha_f64", "S2_givens_f64",
+    "U2_direction_update_f64"};
 static bool on = false;
 static std::vector<hipEvent_t> pool;
 static std::vector<std::pair<int, int>> pending;
 static size_t next = 0;
-static double ms[NKIND];
-static long long cnt[NKIND];
+static double ms[NSLOT];
+static long long cnt[NSLOT];
 static long long dropped = 0;
 static size_t reserved = 0;  // pool slots owned by a captured graph
 static std::mutex mu;
+template <typename T>
 static inline void begin(int kind, hipStream_t s) {
   if (!on) return;
+  if (sizeof(T) == 8) kind += NKIND;
   std::lock_guard<std::mutex> lk(mu);
   if (next + 2 > pool.size()) {
     dropped++;
@@ -722,12 +729,12 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     const int W = tile_p1(pl, elem);
     const size_t lds = sizeof(cx<T>) * W * std::max(na2 * (nb2 + 1), N2 + 1);
     dim3 grid((g.n1 + W - 1) / W, g.n0, nc);
-    prof::begin(prof::P1, s);
+    prof::begin<T>(prof::P1, s);
     hipLaunchKernelGGL(K2.p1, grid, dim3(W * nb2), lds, s, x, xscale, (int)(sizeof(MinresState) / sizeof(double)),
                        phi, mat, spec, tb.tw[2], g, W, st, uk ? partials : nullptr);
     prof::end(s);
     if (uk) {
-      prof::begin(prof::S1, s);
+      prof::begin<T>(prof::S1, s);
       hipLaunchKernelGGL(k_minres_alpha, dim3(nc), dim3(256), 0, s, st, partials, (int)(grid.x * grid.y));
     }
     prof::end(s);
@@ -737,7 +744,7 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
   {
     const int R = rows_p2(pl, elem);
     const size_t lds = sizeof(cx<T>) * R * na1 * (nb1 + 1);
-    prof::begin(prof::P2, s);
+    prof::begin<T>(prof::P2, s);
     hipLaunchKernelGGL(K1.p2f, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, tb.tw[1], g, R, rows,
                        st);
     prof::end(s);
@@ -753,7 +760,7 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
       ft.c[p] = tb.c[p];
     }
     dim3 grid((g.n1 + W - 1) / W, g.k2, nc);
-    prof::begin(prof::P3, s);
+    prof::begin<T>(prof::P3, s);
     const P3Fn<T> fn = sp == 2 ? (identity ? K0.p3s_ident : K0.p3s) : (identity ? K0.p3_ident : K0.p3);
     hipLaunchKernelGGL(fn, grid, dim3(sp * W * nb0), lds, s, spec, tb.tw[0], ft, g, W, (T)(1.0 / (double)g.nvox),
                        st);
@@ -763,7 +770,7 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
   {
     const int R = rows_p2(pl, elem);
     const size_t lds = sizeof(cx<T>) * R * na1 * (nb1 + 1);
-    prof::begin(prof::P4, s);
+    prof::begin<T>(prof::P4, s);
     hipLaunchKernelGGL(K1.p2i, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, tb.tw[1], g, R, rows,
                        st);
     prof::end(s);
@@ -773,11 +780,11 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     const int W = tile_p1(pl, elem);
     const size_t lds = sizeof(cx<T>) * W * std::max(na2 * (nb2 + 1), N2 + 1);
     dim3 grid((g.n1 + W - 1) / W, g.n0, nc);
-    prof::begin(prof::P5, s);
+    prof::begin<T>(prof::P5, s);
     hipLaunchKernelGGL(K2.p5, grid, dim3(W * nb2), lds, s, spec, y, uk, ukm1, partials, tb.tw[2], g, W, st);
     prof::end(s);
     if (uk) {
-      prof::begin(prof::S2, s);
+      prof::begin<T>(prof::S2, s);
       hipLaunchKernelGGL(k_minres_givens, dim3(nc), dim3(256), 0, s, st, partials, (int)(grid.x * grid.y));
     }
     prof::end(s);
@@ -824,7 +831,7 @@ static void enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, const f
   int& id2 = ph[4];
   for (int j = 0; j < count; ++j) {
     apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s);
-    prof::begin(prof::U2, s);
+    prof::begin<T>(prof::U2, s);
     if (vec)
       hipLaunchKernelGGL((k_direction<T, true>), vg, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
     else
@@ -983,7 +990,7 @@ void rve_default_options(rve_options* o) {
   o->scheme = RVE_SCHEME_ROTATED;
   o->check_every = 24;
   o->inner_floor = 3e-2;
-  o->inner_safety = 0.5;
+  o->inner_safety = 0.9;
 }
 
 int32_t rve_supported_length(int32_t n) {
@@ -1006,7 +1013,7 @@ void rve_profile_enable(int32_t on_) {
 
 void rve_profile_reset(void) {
   std::lock_guard<std::mutex> lk(prof::mu);
-  for (int k = 0; k < prof::NKIND; ++k) {
+  for (int k = 0; k < prof::NSLOT; ++k) {
     prof::ms[k] = 0;
     prof::cnt[k] = 0;
   }
@@ -1015,15 +1022,15 @@ void rve_profile_reset(void) {
 
 int32_t rve_profile_read(double* total_ms, int64_t* launches, int32_t max_kinds) {
   std::lock_guard<std::mutex> lk(prof::mu);
-  const int n = std::min<int>(max_kinds, prof::NKIND);
+  const int n = std::min<int>(max_kinds, prof::NSLOT);
   for (int k = 0; k < n; ++k) {
     if (total_ms) total_ms[k] = prof::ms[k];
     if (launches) launches[k] = prof::cnt[k];
   }
-  return prof::NKIND;
+  return prof::NSLOT;
 }
 
-const char* rve_profile_kind_name(int32_t k) { return (k >= 0 && k < prof::NKIND) ? prof::kNames[k] : ""; }
+const char* rve_profile_kind_name(int32_t k) { return (k >= 0 && k < prof::NSLOT) ? prof::kNames[k] : ""; }
 
 const char* rve_last_error(void) { return g_last_error; }
 

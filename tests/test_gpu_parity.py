@@ -435,3 +435,34 @@ def test_every_factorisation_gives_the_same_operator(N, dt, tmp_path):
     tol = 1e-13 if dt == "f64" else 2e-6
     for y in ys[1:]:
         assert _rel(y, ys[0]) < tol
+
+
+def test_profiler_separates_precisions_and_counts_iterations():
+    """The per-kernel profiler keeps FP32-field and FP64-field passes apart: an FP32-mixed solve runs
+    one launch of each pass per MINRES iteration on FP32 fields (plus the skipped tail of the last
+    chunk) and its FP64 residual applies on FP64 fields, with no FP64 direction update."""
+    rve = _rve()
+    n = (32, 32, 32)
+    phi, _ = li.octet_phase_map(n, 0.10)
+    E = li.uniaxial_strain(1e-3)[None]
+    rve.profile_reset()
+    rve.profile_enable(True)
+    try:
+        out = rve.solve(_dev(phi), C1, E, tol=1e-6)
+    finally:
+        rve.profile_enable(False)
+    prof = rve.profile_read()
+    assert out["status"] == 0
+    assert len(prof) == 16
+    its = int(out["iterations"][0])
+    for k in ("P1_stiffness_fft_axis2_alpha", "P2_fft_axis1", "P3_fft_axis0_projection", "P4_ifft_axis1",
+              "P5_ifft_axis2_lanczos", "U2_direction_update"):
+        ms, cnt = prof[k]
+        assert its <= cnt and ms > 0, (k, its, cnt)
+        ms64, cnt64 = prof[k + "_f64"]
+        if k == "U2_direction_update":
+            assert cnt64 == 0
+        else:
+            assert 1 <= cnt64 < its and ms64 > 0, (k, cnt64)
+    rve.profile_reset()
+    assert all(v == (0.0, 0) for v in rve.profile_read().values())
