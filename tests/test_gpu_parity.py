@@ -139,7 +139,8 @@ def _ceff_golden(n, rho):
     return None if d is None else np.array(d["C"])
 
 
-@pytest.mark.parametrize("n,rho", [(32, 0.05), (32, 0.10), (32, 0.20), (64, 0.05), (64, 0.10), (64, 0.20)])
+@pytest.mark.parametrize("n,rho", [(32, 0.05), (32, 0.10), (32, 0.20), (64, 0.05), (64, 0.10), (64, 0.20),
+                                   (128, 0.05), (128, 0.10), (128, 0.20)])
 def test_fp32_mixed_effective_stiffness_vs_oracle(n, rho):
     """Six unit Mandel load cases batched in one call, FP32 operator + FP64 refinement.  The
     residual tolerance is 1e-8: on these compliant lattices a 1e-6 residual still leaves a few 1e-5
