@@ -294,6 +294,8 @@ __global__ void k_minres_givens(MinresState* st, const double* partials, int np)
 }
 
 // U2: d_k = cd_u u_k + cd_d1 d_{k-1} + cd_d2 d_{k-2} (written over d_{k-2}); x += cx d_k.
+// One 16-byte vector per thread over a grid that covers the field once (a grid-stride loop over a
+// fixed grid streamed about 10% slower); every load of the element is issued before its arithmetic.
 template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* uk, T* x, const MinresState* st,
                                                    long long n6) {
@@ -311,6 +313,8 @@ __global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* 
       VT dv = reinterpret_cast<const VT*>(d2 + off)[i];
       const VT uv = reinterpret_cast<const VT*>(uk + off)[i];
       const VT d1v = reinterpret_cast<const VT*>(d1 + off)[i];
+      VT xv;
+      if (mode != 0) xv = reinterpret_cast<const VT*>(x + off)[i];
       T* de = reinterpret_cast<T*>(&dv);
       const T* ue = reinterpret_cast<const T*>(&uv);
       const T* d1e = reinterpret_cast<const T*>(&d1v);
@@ -318,7 +322,6 @@ __global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* 
       for (int e = 0; e < V; ++e) de[e] = a * ue[e] + b * d1e[e] + c * de[e];
       reinterpret_cast<VT*>(d2 + off)[i] = dv;
       if (mode != 0) {
-        VT xv = reinterpret_cast<const VT*>(x + off)[i];
         T* xe = reinterpret_cast<T*>(&xv);
 #pragma unroll
         for (int e = 0; e < V; ++e) xe[e] += (mode == 2 ? xp * d1e[e] : (T)0) + xc * de[e];
@@ -832,10 +835,12 @@ static void enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, const f
   for (int j = 0; j < count; ++j) {
     apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s);
     prof::begin<T>(prof::U2, s);
+    const long long nv = vec ? n6 / Vec16<T>::n : n6;
+    const dim3 ug((unsigned)((nv + kThreads - 1) / kThreads), nc);
     if (vec)
-      hipLaunchKernelGGL((k_direction<T, true>), vg, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
+      hipLaunchKernelGGL((k_direction<T, true>), ug, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
     else
-      hipLaunchKernelGGL((k_direction<T, false>), vg, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
+      hipLaunchKernelGGL((k_direction<T, false>), ug, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
     prof::end(s);
     const int t0 = ia;
     ia = ib;
