@@ -82,7 +82,8 @@ typedef struct {
  * rotated scheme, check_every 24, inner_floor 3e-2, inner_safety 0.9. */
 void rve_default_options(rve_options* opt);
 
-/* 1 if the FFT kernels provide axis length n (n = NA*NB with radix factors 2, 3, 4, 5), else 0. */
+/* 1 if the FFT kernels provide axis length n, else 0: every n in [2, 256] without a prime factor
+ * above 5 (n = NA*NB, each stage a register DFT composed of radix 2, 3, 4 and 5 steps). */
 int32_t rve_supported_length(int32_t n);
 
 /* Host-side validation of a solve_rve call's scalar arguments (no HIP call, no pointer dereference

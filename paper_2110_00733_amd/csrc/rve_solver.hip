@@ -46,6 +46,10 @@ static int len_variants(int n) {
 void register_group_a();
 void register_group_b();
 void register_group_c();
+void register_group_d();
+void register_group_e();
+void register_group_f();
+void register_group_g();
 extern "C" int32_t rve_load_tuning(const char* path);
 static void ensure_registry() {
   static std::once_flag once;
@@ -53,6 +57,10 @@ static void ensure_registry() {
     register_group_a();
     register_group_b();
     register_group_c();
+    register_group_d();
+    register_group_e();
+    register_group_f();
+    register_group_g();
     const char* f = getenv("RVE_TUNE_FILE");
     if (f && f[0]) rve_load_tuning(f);
   });

@@ -40,12 +40,20 @@ def test_library_exports_every_declared_symbol():
     assert sorted(rve.ABI_SYMBOLS + nn.NN_ABI_SYMBOLS) == names
 
 
+def _smooth5(n):
+    for p in (2, 3, 5):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
 def test_supported_lengths():
+    """Every length from 2 to 256 without a prime factor above 5 has kernels; nothing else does."""
     rve = _rve()
-    for n in (2, 3, 4, 5, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256):
-        assert rve.supported_length(n), n
-    for n in (0, 1, 7, 11, 13, 17, 1024):
-        assert not rve.supported_length(n), n
+    for n in range(0, 300):
+        assert rve.supported_length(n) == (2 <= n <= 256 and _smooth5(n)), n
+    assert sum(_smooth5(n) for n in range(2, 257)) == 51
+    assert not rve.supported_length(1024)
 
 
 def test_validation_codes():
