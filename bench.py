@@ -96,7 +96,7 @@ KIND_TO_KERNEL = {  # profiler kind -> rocprofv3 kernel name prefix (FP32 fields
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("rve_kernels.h", "rve_device.h", "rve_solver.hip"):
+    for f in ("rve_kernels.h", "rve_device.h", "rve_solver_kernels.h", "rve_solver.hip"):
         h.update(open(os.path.join(ROOT, "paper_2110_00733_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -25,6 +25,7 @@ struct GridDims {
   int n0, n1, n2, k2;      // k2 = n2/2 + 1
   long long nvox;          // n0*n1*n2
   long long spec_case;     // 6*k2*n0*n1 complex elements per load case
+  int tile, tile_shift;    // n0 tile of P3's spectrum copy (a power of two dividing n0 and NB of axis 0)
 };
 
 // Per-solve MINRES scalars (FP64), one per load case, resident on the device.
@@ -90,6 +91,15 @@ struct FreqTables {
 
 __device__ __forceinline__ long long spec_idx(const GridDims& g, int cs, int k2, int c, int n0, int n1) {
   return ((((long long)cs * g.k2 + k2) * 6 + c) * g.n0 + n0) * (long long)g.n1 + n1;
+}
+// P3's copy of the spectrum: every (case, k2, component) plane stored in tiles of g.tile consecutive
+// n0, [n0 / tile][n1][n0 % tile], so that a pencil along axis 0 reads runs of g.tile values and
+// neighbouring pencils (n1, n1 + 1) are adjacent
+__device__ __forceinline__ long long spec_t_plane(const GridDims& g, int cs, int k2, int c) {
+  return (((long long)cs * g.k2 + k2) * 6 + c) * g.n0 * (long long)g.n1;
+}
+__device__ __forceinline__ long long spec_t_off(const GridDims& g, int n0, int n1) {
+  return (long long)(n0 >> g.tile_shift) * g.n1 * g.tile + (long long)n1 * g.tile + (n0 & (g.tile - 1));
 }
 
 // ---------------------------------------------------------------------------- Krylov scalar steps
@@ -274,42 +284,93 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
 }
 
 // ============================================================================ P2 / P4
-// rows of N1 complex, contiguous; grid (ceil(rows/R)), block R*NB threads
+// Rows of N1 complex, one per (case, k2, component, n0); grid (ceil(rows/R)), block R*NB threads,
+// dyn. LDS R*(NA*(NB+1)+1) complex.  P2 (S < 0) reads rows of spec and writes P3's tiled copy
+// (spec_t_off), P4 (S > 0) reads the tiled copy and writes rows of spec.  The side on spec runs with
+// the element index fastest across lanes (adjacent along a row), the side on the tiled copy with the
+// row index fastest (consecutive n0 at one n1 are adjacent there); the LDS exchange between the two
+// transform stages hands the data from one lane order to the other.
 template <typename T, int NA, int NB, int S>
-__global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, GridDims g, int R,
-                        long long total_rows, const MinresState* __restrict__ st) {
+__global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, cx<T>* __restrict__ spec_t,
+                                               const cx<T>* __restrict__ tw, GridDims g, int R, long long total_rows,
+                                               const MinresState* __restrict__ st) {
   constexpr int N = NA * NB;
   constexpr int TT = NB;
   constexpr int CB = (NA + TT - 1) / TT;
+  constexpr int RSW = NA * (NB + 1) + 1;  // LDS words (complex) per row: odd, so rows fall on distinct banks
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x;
-  const int t = tid % TT, w = tid / TT;
-  const long long rows_per_case = (long long)g.k2 * 6 * g.n0;
-  const long long row = (long long)blockIdx.x * R + w;
-  const int cs = (int)(row / rows_per_case);
-  const bool ok = (row < total_rows) && !(st && st[cs].finish);
-  cx<T>* rp = spec + row * N;
+  const long long row0 = (long long)blockIdx.x * R;
+  const int t_row = tid % TT, w_row = tid / TT;  // element index fastest
+  const int w_til = tid % R, t_til = tid / R;    // row index fastest
+  const int t1 = (S < 0) ? t_row : t_til, w1 = (S < 0) ? w_row : w_til;  // stage A (input side)
+  const int t2 = (S < 0) ? t_til : t_row, w2 = (S < 0) ? w_til : w_row;  // stage B (output side)
+  // row row0 + w lies in plane p (case, k2, component) at n0; the block's first row is split once
+  // (uniform), the lanes step from it (R may not divide n0)
+  const long long p0 = row0 / g.n0;
+  const int n00 = (int)(row0 - p0 * g.n0);
+  const int planes_per_case = 6 * g.k2;
+  auto locate = [&](int w, long long* p, int* n0) {
+    int q = n00 + w;
+    long long pp = p0;
+    while (q >= g.n0) {
+      q -= g.n0;
+      ++pp;
+    }
+    *p = pp;
+    *n0 = q;
+  };
+  auto live = [&](long long r, long long p) {  // p < 65535 cases * 6 * k2 fits 32 bits
+    return r < total_rows && !(st && st[(int)p / planes_per_case].finish);
+  };
+  const long long ra = row0 + w1;
+  long long pa;
+  int n0a;
+  locate(w1, &pa, &n0a);
+  const bool oka = live(ra, pa);
+  // offset of element 0 of the row in the tiled copy (element j at + j * tile)
+  // the tiled side addresses from the block's first plane with 32-bit offsets (the block's rows span
+  // at most a few planes of n0*N1 <= 2^16 elements), so the loads and stores take a uniform base
+  const cx<T>* tblk = spec_t + p0 * g.n0 * (long long)N;
+  const unsigned ta = oka ? (unsigned)((pa - p0) * g.n0 * N + spec_t_off(g, n0a, 0)) : 0u;
   cx<T> z[NA];
+  if (S < 0) {
 #pragma unroll
-  for (int i = 0; i < NA; ++i) z[i] = ok ? rp[t + NB * i] : mk<T>(0, 0);
+    for (int i = 0; i < NA; ++i) z[i] = oka ? spec[ra * N + t1 + NB * i] : mk<T>(0, 0);
+  } else {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) z[i] = oka ? tblk[ta + (unsigned)((t1 + NB * i) * g.tile)] : mk<T>(0, 0);
+  }
   DFT<NA, S, T>::run(z);
 #pragma unroll
-  for (int a = 1; a < NA; ++a) z[a] = (S < 0) ? cmul(z[a], tw[(t * a) % N]) : cmulc(z[a], tw[(t * a) % N]);
+  for (int a = 1; a < NA; ++a) z[a] = (S < 0) ? cmul(z[a], tw[(t1 * a) % N]) : cmulc(z[a], tw[(t1 * a) % N]);
 #pragma unroll
-  for (int a = 0; a < NA; ++a) lds[(w * NA + a) * (NB + 1) + t] = z[a];
+  for (int a = 0; a < NA; ++a) lds[w1 * RSW + a * (NB + 1) + t1] = z[a];
   lds_barrier();
+  const long long rb = row0 + w2;
+  long long pb;
+  int n0b;
+  locate(w2, &pb, &n0b);
+  const bool okb = live(rb, pb);
+  const unsigned tb = okb ? (unsigned)((pb - p0) * g.n0 * N + spec_t_off(g, n0b, 0)) : 0u;
+  cx<T>* tblk_w = spec_t + p0 * g.n0 * (long long)N;
 #pragma unroll
   for (int j = 0; j < CB; ++j) {
-    const int a = t + TT * j;
+    const int a = t2 + TT * j;
     if (a < NA) {
       cx<T> yb[NB];
 #pragma unroll
-      for (int u = 0; u < NB; ++u) yb[u] = lds[(w * NA + a) * (NB + 1) + u];
+      for (int u = 0; u < NB; ++u) yb[u] = lds[w2 * RSW + a * (NB + 1) + u];
       DFT<NB, S, T>::run(yb);
-      if (ok) {
+      if (okb) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) rp[a + NA * b] = yb[b];
+        for (int b = 0; b < NB; ++b) {
+          if (S > 0)
+            spec[rb * N + a + NA * b] = yb[b];
+          else
+            tblk_w[tb + (unsigned)((a + NA * b) * g.tile)] = yb[b];
+        }
       }
     }
   }
@@ -371,18 +432,19 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
   // the memory-side cache, and P4 (ascending again) then starts on the planes written last here
   const int k2 = g.k2 - 1 - (int)blockIdx.y;
   const int tid = threadIdx.x;
-  const int w = tid % W, t = tid / W;
+  const int t = tid % NB, w = tid / NB;  // a pencil's threads are adjacent lanes
   const int k1 = blockIdx.x * W + w;
   const bool ok = k1 < g.n1;
   const int RS = NB * W + 1;
   const long long pstride = (long long)g.n0 * g.n1;  // component stride inside one k2 plane
-  cx<T>* base = spec + spec_idx(g, cs, k2, 0, 0, ok ? k1 : 0);
+  cx<T>* base = spec + spec_t_plane(g, cs, k2, 0) + spec_t_off(g, 0, ok ? k1 : 0);
+  const long long toff = spec_t_off(g, t, 0);  // element t + NB i at toff + i NB n1 (tile divides NB)
 
   cx<T> D[6][E];
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) D[c][i] = ok ? base[c * pstride + (long long)(t + NB * i) * g.n1] : mk<T>(0, 0);
+    for (int i = 0; i < NA; ++i) D[c][i] = ok ? base[c * pstride + toff + (long long)i * (NB * g.n1)] : mk<T>(0, 0);
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
@@ -391,14 +453,14 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
     for (int a = 1; a < NA; ++a) D[c][a] = cmul(D[c][a], tw[(t * a) % N]);
     lds_barrier();
 #pragma unroll
-    for (int a = 0; a < NA; ++a) lds[a * RS + t * W + w] = D[c][a];
+    for (int a = 0; a < NA; ++a) lds[a * RS + w * NB + t] = D[c][a];
     lds_barrier();
 #pragma unroll
     for (int j = 0; j < CB; ++j) {
       const int a = t + TT * j;
       if (a < NA) {
 #pragma unroll
-        for (int u = 0; u < NB; ++u) D[c][j * NB + u] = lds[a * RS + u * W + w];
+        for (int u = 0; u < NB; ++u) D[c][j * NB + u] = lds[a * RS + w * NB + u];
         DFT<NB, -1, T>::run(&D[c][j * NB]);
       }
     }
@@ -449,16 +511,16 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
       const int a = t + TT * j;
       if (a < NA) {
 #pragma unroll
-        for (int u = 0; u < NB; ++u) lds[a * RS + u * W + w] = D[c][j * NB + u];
+        for (int u = 0; u < NB; ++u) lds[a * RS + w * NB + u] = D[c][j * NB + u];
       }
     }
     lds_barrier();
 #pragma unroll
-    for (int a = 0; a < NA; ++a) D[c][a] = lds[a * RS + t * W + w];
+    for (int a = 0; a < NA; ++a) D[c][a] = lds[a * RS + w * NB + t];
     DFT<NA, 1, T>::run(D[c]);
     if (ok) {
 #pragma unroll
-      for (int i = 0; i < NA; ++i) base[c * pstride + (long long)(t + NB * i) * g.n1] = D[c][i];
+      for (int i = 0; i < NA; ++i) base[c * pstride + toff + (long long)i * (NB * g.n1)] = D[c][i];
     }
   }
 }
@@ -491,20 +553,21 @@ __global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__
   const int tid = threadIdx.x;
   const int WNB = W * NB;  // a multiple of 64: each half is whole waves, so h is wave-uniform
   const int q = tid % WNB, h = __builtin_amdgcn_readfirstlane(tid / WNB);
-  const int w = q % W, t = q / W;
+  const int t = q % NB, w = q / NB;  // a pencil's threads are adjacent lanes
   const int k1 = blockIdx.x * W + w;
   const bool ok = k1 < g.n1;
   const int RS = NB * W + 1;
   cx<T>* lds_all = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* lds = lds_all + h * NA * RS;
   const long long pstride = (long long)g.n0 * g.n1;
-  cx<T>* base = spec + spec_idx(g, cs, k2, 0, 0, ok ? k1 : 0) + (long long)(3 * h) * pstride;
+  cx<T>* base = spec + spec_t_plane(g, cs, k2, 3 * h) + spec_t_off(g, 0, ok ? k1 : 0);
+  const long long toff = spec_t_off(g, t, 0);  // element t + NB i at toff + i NB n1 (tile divides NB)
 
   cx<T> D[3][E];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) D[c][i] = ok ? base[c * pstride + (long long)(t + NB * i) * g.n1] : mk<T>(0, 0);
+    for (int i = 0; i < NA; ++i) D[c][i] = ok ? base[c * pstride + toff + (long long)i * (NB * g.n1)] : mk<T>(0, 0);
 #pragma unroll
     for (int i = NA; i < E; ++i) D[c][i] = mk<T>(0, 0);
   }
@@ -523,14 +586,14 @@ __global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__
     for (int a = 1; a < NA; ++a) D[c][a] = cmul(D[c][a], HOIST ? twv[HOIST ? a : 0] : tw[(t * a) % N]);
     lds_barrier();
 #pragma unroll
-    for (int a = 0; a < NA; ++a) lds[a * RS + t * W + w] = D[c][a];
+    for (int a = 0; a < NA; ++a) lds[a * RS + w * NB + t] = D[c][a];
     lds_barrier();
 #pragma unroll
     for (int j = 0; j < CB; ++j) {
       const int a = t + TT * j;
       if (a < NA) {
 #pragma unroll
-        for (int u = 0; u < NB; ++u) D[c][j * NB + u] = lds[a * RS + u * W + w];
+        for (int u = 0; u < NB; ++u) D[c][j * NB + u] = lds[a * RS + w * NB + u];
         DFT<NB, -1, T>::run(&D[c][j * NB]);
       }
     }
@@ -617,16 +680,16 @@ __global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__
       const int a = t + TT * j;
       if (a < NA) {
 #pragma unroll
-        for (int u = 0; u < NB; ++u) lds[a * RS + u * W + w] = D[c][j * NB + u];
+        for (int u = 0; u < NB; ++u) lds[a * RS + w * NB + u] = D[c][j * NB + u];
       }
     }
     lds_barrier();
 #pragma unroll
-    for (int a = 0; a < NA; ++a) D[c][a] = lds[a * RS + t * W + w];
+    for (int a = 0; a < NA; ++a) D[c][a] = lds[a * RS + w * NB + t];
     DFT<NA, 1, T>::run(D[c]);
     if (ok) {
 #pragma unroll
-      for (int i = 0; i < NA; ++i) base[c * pstride + (long long)(t + NB * i) * g.n1] = D[c][i];
+      for (int i = 0; i < NA; ++i) base[c * pstride + toff + (long long)i * (NB * g.n1)] = D[c][i];
     }
   }
 }

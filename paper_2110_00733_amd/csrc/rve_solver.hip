@@ -127,312 +127,11 @@ static void flush() {
 }
 }  // namespace prof
 
-// ============================================================================ small kernels
-constexpr int kRedBlocks = 2048;  // blocks per case for streaming vector kernels (and their partials)
-constexpr int kThreads = 256;
+}  // namespace rve
 
-// Frequency and twiddle tables per axis:
-//   tw[m] = exp(-2 pi i m / N)                                 (transform twiddles)
-//   rotated scheme:    s[m] = sin(q/2)/h, c[m] = cos(q/2)       (eq. freqrot, real direction)
-//   continuous scheme: s[m] = q/h,        c[m] = 1               (eq. freq)
-//   q = 2 pi k/N, k = m for m <= (N-1)/2 else m - N; at a Nyquist index c = 0 exactly, and with
-//   the zero-all Nyquist reading s = 0 too, so the projection vanishes there.
-template <typename T>
-__global__ void k_tables(cx<T>* tw, T* s, T* c, int N, double h, int scheme, int nyq_zero_all) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= N) return;
-  double sn, cs;
-  sincospi(-2.0 * (double)m / (double)N, &sn, &cs);
-  tw[m] = mk<T>((T)cs, (T)sn);
-  const int k = (m <= (N - 1) / 2) ? m : m - N;
-  const bool nyq = (N % 2 == 0) && (2 * m == N);
-  double sh, ch;
-  sincospi((double)k / (double)N, &sh, &ch);  // half angle q/2 = pi k / N
-  double sv, cv;
-  if (scheme == RVE_SCHEME_CONTINUOUS) {
-    sv = 2.0 * kPi * (double)k / (double)N / h;
-    cv = 1.0;
-  } else {
-    sv = sh / h;
-    cv = ch;
-  }
-  if (nyq) {
-    cv = 0.0;
-    // the continuous scheme always zeroes Nyquist frequencies (otherwise the projection would not
-    // be even in k and the real-to-complex symmetry of the spectrum would break)
-    if (nyq_zero_all || scheme == RVE_SCHEME_CONTINUOUS) sv = 0.0;
-  }
-  s[m] = (T)sv;
-  c[m] = (T)cv;
-}
+#include "rve_solver_kernels.h"
 
-template <typename T>
-__global__ void k_fill_const(T* x, const double* E /* [nc][6] */, long long nvox) {
-  const int cs = blockIdx.y;
-  T* xc = x + (long long)cs * 6 * nvox;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < 6 * nvox; i += (long long)gridDim.x * blockDim.x)
-    xc[i] = (T)E[cs * 6 + i / nvox];
-}
-
-template <typename T>
-__global__ void k_zero(T* x, long long n) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    x[i] = (T)0;
-}
-
-// out = alpha * a + beta * b (per case), partial sums of out^2
-template <typename Ta, typename To>
-__global__ void k_lincomb(To* out, const Ta* a, double alpha, const double* b, double beta, long long n6,
-                          double* partials) {
-  __shared__ double red[16];
-  const int cs = blockIdx.y;
-  const long long off = (long long)cs * n6;
-  double acc = 0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n6; i += (long long)gridDim.x * blockDim.x) {
-    double v = alpha * (double)a[off + i] + (b ? beta * b[off + i] : 0.0);
-    To o = (To)v;
-    out[off + i] = o;
-    acc += (double)o * (double)o;
-  }
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0 && partials) partials[(long long)cs * gridDim.x + blockIdx.x] = s;
-}
-
-// x64 += (double) d  (per case, only where mask[cs] != 0)
-template <typename Td>
-__global__ void k_accum(double* x64, const Td* d, long long n6, const int* active) {
-  const int cs = blockIdx.y;
-  if (active && !active[cs]) return;
-  const long long off = (long long)cs * n6;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n6; i += (long long)gridDim.x * blockDim.x)
-    x64[off + i] += (double)d[off + i];
-}
-
-// deterministic per-case sum of partials[cs][0..np) -> out[cs * ostride]
-__global__ void k_sum_partials(const double* partials, int np, double* out, int ostride, int take_sqrt) {
-  __shared__ double red[16];
-  const int cs = blockIdx.x;
-  double acc = 0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[(long long)cs * np + i];
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) out[(long long)cs * ostride] = take_sqrt ? sqrt(s) : s;
-}
-
-// ---------------------------------------------------------------------------- MINRES scalars
-// Per-case bookkeeping of the whole solve.
-struct CaseInfo {
-  double bnorm;       // ||b||
-  double rnorm;       // ||b - A x64|| (last true residual)
-  int active;         // this case still needs an inner sweep
-  int iters;          // MINRES iterations summed over sweeps
-  int status;         // worst inner status
-  int warm_rejected;  // the warm start was replaced by zero
-  double r0;          // ||b - A x0|| of the start (before a rejected warm start is dropped)
-};
-
-// Start an inner MINRES on A d = r with u_1 = r (partials hold ||u_1||^2).
-__global__ void k_minres_init(MinresState* st, const double* partials, int np, CaseInfo* ci, double tol,
-                              double safety, double inner_floor, int max_iter) {
-  __shared__ double red[16];
-  const int cs = blockIdx.x;
-  double acc = 0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[(long long)cs * np + i];
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) {
-    MinresState& S = st[cs];
-    const double beta = sqrt(s);
-    S.beta = beta;
-    S.ib = beta > 0 ? 1.0 / beta : 0.0;
-    S.ib_prev = 0.0;
-    S.alpha = 0.0;
-    S.c1 = S.c2 = 1.0;
-    S.s1 = S.s2 = 0.0;
-    S.phibar = beta;
-    S.tol_abs = fmax(safety * tol * ci[cs].bnorm, inner_floor * beta);
-    S.cu_v = S.cu_vp = S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = S.cx_prev = 0.0;
-    S.xmode = 0;
-    S.pending = 0;
-    S.iter = 0;
-    S.max_iter = max_iter - ci[cs].iters;
-    S.status = 0;
-    S.finish = (!ci[cs].active || beta <= S.tol_abs || S.max_iter <= 0) ? 1 : 0;
-    S.done = 0;
-  }
-}
-
-// 16-byte vector access for the streaming vector kernels (falls back to scalars when a case's
-// field length is not a multiple of the vector width).
-template <typename T>
-struct Vec16;
-template <>
-struct Vec16<float> {
-  using type = float4;
-  static constexpr int n = 4;
-};
-template <>
-struct Vec16<double> {
-  using type = double2;
-  static constexpr int n = 2;
-};
-
-// S1: alpha_k from the P1 partials (fixed-order sum).  Also retires a case whose previous iteration
-// finished (that iteration's U2 has run by now).
-__global__ void k_minres_alpha(MinresState* st, const double* partials, int np) {
-  __shared__ double red[16];
-  const int cs = blockIdx.x;
-  MinresState& S = st[cs];
-  if (S.done) return;
-  if (S.finish) {
-    __syncthreads();
-    if (threadIdx.x == 0) S.done = 1;
-    return;
-  }
-  const double s = sum_partials(partials + (long long)cs * np, np, red);
-  if (threadIdx.x == 0) alpha_step(S, s);
-}
-
-// S2: beta_{k+1} from the P5 partials, Givens step, convergence test.
-__global__ void k_minres_givens(MinresState* st, const double* partials, int np) {
-  __shared__ double red[16];
-  const int cs = blockIdx.x;
-  MinresState& S = st[cs];
-  if (S.done) return;
-  const double s = sum_partials(partials + (long long)cs * np, np, red);
-  if (threadIdx.x == 0) givens_step(S, s);
-}
-
-// U2: d_k = cd_u u_k + cd_d1 d_{k-1} + cd_d2 d_{k-2} (written over d_{k-2}); x += cx d_k.
-// One 16-byte vector per thread over a grid that covers the field once (a grid-stride loop over a
-// fixed grid streamed about 10% slower); every load of the element is issued before its arithmetic.
-template <typename T, bool VEC>
-__global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* uk, T* x, const MinresState* st,
-                                                   long long n6) {
-  const int cs = blockIdx.y;
-  const MinresState& S = st[cs];
-  if (S.done) return;
-  const T a = (T)S.cd_u, b = (T)S.cd_d1, c = (T)S.cd_d2, xc = (T)S.cx, xp = (T)S.cx_prev;
-  const int mode = S.xmode;  // uniform per block (one case)
-  const long long off = (long long)cs * n6;
-  constexpr int V = VEC ? Vec16<T>::n : 1;
-  using VT = typename Vec16<T>::type;
-  const long long nv = n6 / V;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
-    if constexpr (VEC) {
-      VT dv = reinterpret_cast<const VT*>(d2 + off)[i];
-      const VT uv = reinterpret_cast<const VT*>(uk + off)[i];
-      const VT d1v = reinterpret_cast<const VT*>(d1 + off)[i];
-      VT xv;
-      if (mode != 0) xv = reinterpret_cast<const VT*>(x + off)[i];
-      T* de = reinterpret_cast<T*>(&dv);
-      const T* ue = reinterpret_cast<const T*>(&uv);
-      const T* d1e = reinterpret_cast<const T*>(&d1v);
-#pragma unroll
-      for (int e = 0; e < V; ++e) de[e] = a * ue[e] + b * d1e[e] + c * de[e];
-      reinterpret_cast<VT*>(d2 + off)[i] = dv;
-      if (mode != 0) {
-        T* xe = reinterpret_cast<T*>(&xv);
-#pragma unroll
-        for (int e = 0; e < V; ++e) xe[e] += (mode == 2 ? xp * d1e[e] : (T)0) + xc * de[e];
-        reinterpret_cast<VT*>(x + off)[i] = xv;
-      }
-    } else {
-      const T d1s = d1[off + i];
-      const T d = a * uk[off + i] + b * d1s + c * d2[off + i];
-      d2[off + i] = d;
-      if (mode != 0) x[off + i] += (mode == 2 ? xp * d1s : (T)0) + xc * d;
-    }
-  }
-}
-
-// Inner sweep bookkeeping: add iterations, record status.
-__global__ void k_sweep_done(const MinresState* st, CaseInfo* ci, int nc) {
-  const int cs = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cs >= nc || !ci[cs].active) return;
-  ci[cs].iters += st[cs].iter;
-  if (st[cs].status != 0 && st[cs].status != RVE_NOT_CONVERGED) ci[cs].status = st[cs].status;
-  if (st[cs].status == RVE_NOT_CONVERGED) ci[cs].status = RVE_NOT_CONVERGED;
-}
-
-// After a true-residual evaluation: rnorm from the summed partial; decide whether another sweep runs.
-__global__ void k_residual_update(CaseInfo* ci, const double* sums, int nc, double tol, int max_iter) {
-  const int cs = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cs >= nc) return;
-  ci[cs].rnorm = sqrt(sums[cs]);
-  const bool conv = ci[cs].bnorm == 0.0 || ci[cs].rnorm <= tol * ci[cs].bnorm;
-  const bool bad = ci[cs].status == RVE_ENONFINITE || ci[cs].status == RVE_BREAKDOWN;
-  ci[cs].active = (!conv && !bad && ci[cs].iters < max_iter) ? 1 : 0;
-}
-
-// A warm start that does not reduce the residual below ||b|| is dropped: x = 0, r = b (the zero
-// start, bit for bit).  Grid (blocks, nc).
-__global__ void k_warm_fallback(double* x64, double* r64, const double* b64, CaseInfo* ci, long long n6) {
-  const int cs = blockIdx.y;
-  if (!(ci[cs].bnorm > 0.0 && ci[cs].rnorm >= ci[cs].bnorm)) return;
-  const long long off = (long long)cs * n6;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n6; i += (long long)gridDim.x * blockDim.x) {
-    x64[off + i] = 0.0;
-    r64[off + i] = b64[off + i];
-  }
-}
-// after k_warm_fallback: record the rejection, the residual is now ||b||
-__global__ void k_residual_update_fallback(CaseInfo* ci, int nc) {
-  const int cs = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cs >= nc) return;
-  ci[cs].r0 = ci[cs].rnorm;
-  if (!(ci[cs].bnorm > 0.0 && ci[cs].rnorm >= ci[cs].bnorm)) return;
-  ci[cs].warm_rejected = 1;
-  ci[cs].rnorm = ci[cs].bnorm;
-}
-
-// Post-processing: sigma = C(x) (Ebar + eps) in FP64, write strain/stress in the output type,
-// per-block partial sums of each stress component.
-template <typename To>
-__global__ void k_post(const double* x64, const float* phi, Material<double> mat, const double* E, To* strain_out,
-                       To* stress_out, long long nvox, double* partials /* [nc][6][blocks] */) {
-  __shared__ double red[16];
-  const int cs = blockIdx.y;
-  const long long off = (long long)cs * 6 * nvox;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (long long)gridDim.x * blockDim.x) {
-    double e[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const double f = x64[off + c * nvox + v];
-      if (strain_out) strain_out[off + c * nvox + v] = (To)f;
-      e[c] = E[cs * 6 + c] + f;
-    }
-    const double ph = phi[v];
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      double s = 0, s0 = 0;
-#pragma unroll
-      for (int b = 0; b < 6; ++b) {
-        s += mat.Cd[a * 6 + b] * e[b];
-        s0 += mat.C0[a * 6 + b] * e[b];
-      }
-      const double sig = ph * s + s0;
-      acc[a] += sig;
-      if (stress_out) stress_out[off + a * nvox + v] = (To)sig;
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 6; ++a) {
-    const double s = block_sum(acc[a], red);
-    if (threadIdx.x == 0) partials[((long long)cs * 6 + a) * gridDim.x + blockIdx.x] = s;
-  }
-}
-
-// phi validity: counts of non-finite and out-of-range entries
-__global__ void k_check_phi(const float* phi, long long n, int* bad) {
-  int nb = 0, nr = 0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const float v = phi[i];
-    if (!isfinite(v)) nb++;
-    else if (v < 0.0f || v > 1.0f) nr++;
-  }
-  if (nb) atomicAdd(&bad[0], nb);
-  if (nr) atomicAdd(&bad[1], nr);
-}
+namespace rve {
 
 // ============================================================================ plan + workspace
 static long long align_up(long long v, long long a) { return (v + a - 1) / a * a; }
@@ -513,7 +212,7 @@ static int tile_p3(const Plan& pl, int elem) { return tile_p3_for(pl, elem, spli
 static int rows_p2(const Plan& pl, int elem) {
   const int na = axis(pl, elem, 1)->na, nb = axis(pl, elem, 1)->nb;
   int R = pl.t[elem == 8].R2;
-  while (R > 1 && (R * nb > 256 || 2LL * elem * R * na * (nb + 1) > kLdsCap)) R /= 2;
+  while (R > 1 && (R * nb > 256 || 2LL * elem * R * (na * (nb + 1) + 1) > kLdsCap)) R /= 2;
   return R;
 }
 
@@ -543,6 +242,8 @@ static bool make_plan(const rve_grid* grid, Plan* pl) {
   g.n2 = pl->n[2];
   g.k2 = g.n2 / 2 + 1;
   g.nvox = (long long)g.n0 * g.n1 * g.n2;
+  g.tile = 1;  // set per apply from the axis-0 factorisation in use (apply_op)
+  g.tile_shift = 0;
   g.spec_case = 6LL * g.k2 * g.n0 * g.n1;
   {
     int dev = 0, lds = 0;
@@ -610,7 +311,7 @@ static Layout make_layout(const Plan& pl, int nc, int precision, bool solve) {
   L.off_tab32 = take(tab_bytes(pl, 4));
   L.off_tab64 = take(tab_bytes(pl, 8));
   if (precision == RVE_FP32_MIXED) {
-    L.off_spec32 = take(8 * g.spec_case * nc);
+    L.off_spec32 = take(2 * 8 * g.spec_case * nc);  // plane-major half spectrum + P3's tiled copy
     if (solve) {
       for (int i = 0; i < 3; ++i) L.off_u32[i] = take(4 * n6);
       for (int i = 0; i < 2; ++i) L.off_d32[i] = take(4 * n6);
@@ -620,7 +321,7 @@ static Layout make_layout(const Plan& pl, int nc, int precision, bool solve) {
     for (int i = 0; i < 3; ++i) L.off_u64[i] = take(8 * n6);
     for (int i = 0; i < 2; ++i) L.off_d64[i] = take(8 * n6);
   }
-  if (solve || precision == RVE_FP64) L.off_spec64 = take(16 * g.spec_case * nc);
+  if (solve || precision == RVE_FP64) L.off_spec64 = take(2 * 16 * g.spec_case * nc);
   if (solve) {
     L.off_x64 = take(8 * n6);
     L.off_b64 = take(8 * n6);
@@ -725,7 +426,6 @@ template <typename T>
 static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, const float* phi,
                      const Material<T>& mat, const Tables<T>& tb, cx<T>* spec, T* y, const T* uk, const T* ukm1,
                      double* partials, MinresState* st, int identity, hipStream_t s) {
-  const GridDims& g = pl.g;
   constexpr int el = (int)sizeof(T);
   const LenKernels<T>& K0 = axis(pl, el, 0)->k<T>();
   const LenKernels<T>& K1 = axis(pl, el, 1)->k<T>();
@@ -733,6 +433,13 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
   const int na2 = axis(pl, el, 2)->na, nb2 = axis(pl, el, 2)->nb;
   const int na1 = axis(pl, el, 1)->na, nb1 = axis(pl, el, 1)->nb;
   const int na0 = axis(pl, el, 0)->na, nb0 = axis(pl, el, 0)->nb;
+  // tile of P3's spectrum copy: the largest power of two (<= 16) dividing both n0 and the threads
+  // per pencil, so that a thread's pencil elements t + nb0 i sit at a fixed stride in the copy
+  GridDims g = pl.g;
+  while (g.tile < 16 && g.n0 % (2 * g.tile) == 0 && nb0 % (2 * g.tile) == 0) {
+    g.tile *= 2;
+    g.tile_shift++;
+  }
   const int N2 = g.n2;
   const int elem = (int)sizeof(T);
   // P1
@@ -750,14 +457,15 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     }
     prof::end(s);
   }
-  // P2
+  // P2 (rows of spec -> P3's tiled copy, the second half of the spectrum buffer)
   const long long rows = (long long)nc * g.k2 * 6 * g.n0;
+  cx<T>* spec_t = spec + (long long)nc * g.spec_case;
   {
     const int R = rows_p2(pl, elem);
-    const size_t lds = sizeof(cx<T>) * R * na1 * (nb1 + 1);
+    const size_t lds = sizeof(cx<T>) * R * (na1 * (nb1 + 1) + 1);
     prof::begin<T>(prof::P2, s);
-    hipLaunchKernelGGL(K1.p2f, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, tb.tw[1], g, R, rows,
-                       st);
+    hipLaunchKernelGGL(K1.p2f, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, spec_t, tb.tw[1], g,
+                       R, rows, st);
     prof::end(s);
   }
   // P3
@@ -773,17 +481,17 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     dim3 grid((g.n1 + W - 1) / W, g.k2, nc);
     prof::begin<T>(prof::P3, s);
     const P3Fn<T> fn = sp == 2 ? (identity ? K0.p3s_ident : K0.p3s) : (identity ? K0.p3_ident : K0.p3);
-    hipLaunchKernelGGL(fn, grid, dim3(sp * W * nb0), lds, s, spec, tb.tw[0], ft, g, W, (T)(1.0 / (double)g.nvox),
+    hipLaunchKernelGGL(fn, grid, dim3(sp * W * nb0), lds, s, spec_t, tb.tw[0], ft, g, W, (T)(1.0 / (double)g.nvox),
                        st);
     prof::end(s);
   }
-  // P4
+  // P4 (P3's tiled copy -> rows of spec)
   {
     const int R = rows_p2(pl, elem);
-    const size_t lds = sizeof(cx<T>) * R * na1 * (nb1 + 1);
+    const size_t lds = sizeof(cx<T>) * R * (na1 * (nb1 + 1) + 1);
     prof::begin<T>(prof::P4, s);
-    hipLaunchKernelGGL(K1.p2i, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, tb.tw[1], g, R, rows,
-                       st);
+    hipLaunchKernelGGL(K1.p2i, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, spec_t, tb.tw[1], g,
+                       R, rows, st);
     prof::end(s);
   }
   // P5
