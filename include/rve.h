@@ -109,7 +109,9 @@ size_t rve_workspace_bytes(const rve_grid* grid, int32_t n_cases, const rve_opti
  *                         macro strains e_J this is column J of the effective stiffness
  *   iterations            host int32 [n_cases]: MINRES iterations (operator applications in the loop)
  *   rel_residual          host double [n_cases]: ||b - A eps|| / ||b|| recomputed in FP64 at exit
- * Returns the worst status over the load cases. */
+ * Work is queued on hip_stream and on a second stream the library creates once per host thread and
+ * device (default priority), joined back into hip_stream before every host check; the call returns
+ * after hip_stream has finished.  Returns the worst status over the load cases. */
 rve_status solve_rve(const rve_grid* grid, const float* voxel_fraction_field, const double* phase_stiffness,
                      const double* macro_strain, int32_t n_cases, const rve_options* opt, const void* eps0,
                      void* strain_out, void* stress_out, double* eff_stress, int32_t* iterations,
@@ -166,7 +168,8 @@ rve_status rve_apply(const rve_grid* grid, const float* voxel_fraction_field, co
  * passes on FP32 fields, kinds 8-15 (names ending in _f64) the same passes on FP64 fields.
  * rve_profile_read fills total milliseconds and launch counts for up to max_kinds kinds and
  * returns the number of kinds (16).  Profiled solves launch their kernels directly (no graph
- * replay), so each launch can be bracketed; kernel durations do not depend on the launch path.
+ * replay) and one at a time, so each launch can be bracketed and is timed alone; an unprofiled
+ * solve runs U2 on a second stream beside the next iteration's P3 (solve_rve).
  * Launch counts include the iterations of the last launched chunk after convergence, whose kernels
  * return at once (a few microseconds each); divide by the iteration count for the time of a
  * working launch. */

@@ -28,6 +28,14 @@ struct GridDims {
   int tile, tile_shift;    // n0 tile of P3's spectrum copy (a power of two dividing n0 and NB of axis 0)
 };
 
+// The U2 coefficients of one iteration, copied out by S2 into one of two slots (iteration parity):
+// U2 runs on a second stream beside the next iteration's operator passes, which change the state.
+struct U2Coef {
+  double cd_u, cd_d1, cd_d2, cx, cx_prev;
+  int xmode;   // as MinresState::xmode
+  int active;  // 0: the case had finished before this iteration; U2 does nothing
+};
+
 // Per-solve MINRES scalars (FP64), one per load case, resident on the device.
 struct MinresState {
   double beta, ib, ib_prev;          // beta_k, 1/beta_k, 1/beta_{k-1} (deferred normalisation of v)
@@ -43,6 +51,7 @@ struct MinresState {
   int xmode;    // U2's solution update: 0 defer, 1 x += cx d_k, 2 x += cx_prev d_{k-1} + cx d_k
   int pending;  // a deferred cx_prev d_{k-1} is owed to x
   int pad;
+  U2Coef u2[2];  // U2's coefficients of the last two iterations (slot = iteration parity in the chunk)
 };
 
 // U2 touches x only every second iteration: the update of an even iteration is deferred and added

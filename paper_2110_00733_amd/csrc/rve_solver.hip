@@ -1,10 +1,11 @@
 // Host driver and Krylov kernels of the gfx950 Galerkin-FFT homogenization solver (C ABI in rve.h).
 //
-// One MINRES iteration is eight launches on one stream, no host involvement:
+// One MINRES iteration is eight launches, no host involvement:
 //   P1 stiffness + FFT axis 2, with per-block partials of alpha = <v, C v>;  S1 alpha (one block)
 //   P2, P3 (projection), P4 transforms
 //   P5 inverse FFT axis 2 fused with the Lanczos three-term update and ||u_{k+1}||^2 partials
-//   S2 Givens QR step + convergence test (one block);  U2 search direction + solution update.
+//   S2 Givens QR step + convergence test (one block);  U2 search direction + solution update, on a
+//   second stream beside the next iteration's P3 (see U2Side).
 // Vectors carry a deferred normalisation: the Lanczos vector v_k is stored unscaled (u_k) and its
 // 1/beta_k is applied inside the consumers (P1 stiffness, P5 update, U2).
 // FP32_MIXED: fields and transforms in FP32, Krylov scalars and all inner products in FP64; the
@@ -425,7 +426,8 @@ static Material<T> make_material(const double* Cvoid, const double* Csolid) {
 template <typename T>
 static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, const float* phi,
                      const Material<T>& mat, const Tables<T>& tb, cx<T>* spec, T* y, const T* uk, const T* ukm1,
-                     double* partials, MinresState* st, int identity, hipStream_t s) {
+                     double* partials, MinresState* st, int identity, hipStream_t s, int u2_slot = 0,
+                     hipEvent_t before_p5 = nullptr, hipEvent_t after_p2 = nullptr) {
   constexpr int el = (int)sizeof(T);
   const LenKernels<T>& K0 = axis(pl, el, 0)->k<T>();
   const LenKernels<T>& K1 = axis(pl, el, 1)->k<T>();
@@ -467,6 +469,7 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     hipLaunchKernelGGL(K1.p2f, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, spec_t, tb.tw[1], g,
                        R, rows, st);
     prof::end(s);
+    if (after_p2) (void)hipEventRecord(after_p2, s);
   }
   // P3
   {
@@ -499,12 +502,15 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     const int W = tile_p1(pl, elem);
     const size_t lds = sizeof(cx<T>) * W * std::max(na2 * (nb2 + 1), N2 + 1);
     dim3 grid((g.n1 + W - 1) / W, g.n0, nc);
+    // P5 overwrites the field an earlier iteration's U2 (second stream) may still be reading
+    if (before_p5) (void)hipStreamWaitEvent(s, before_p5, 0);
     prof::begin<T>(prof::P5, s);
     hipLaunchKernelGGL(K2.p5, grid, dim3(W * nb2), lds, s, spec, y, uk, ukm1, partials, tb.tw[2], g, W, st);
     prof::end(s);
     if (uk) {
       prof::begin<T>(prof::S2, s);
-      hipLaunchKernelGGL(k_minres_givens, dim3(nc), dim3(256), 0, s, st, partials, (int)(grid.x * grid.y));
+      hipLaunchKernelGGL(k_minres_givens, dim3(nc), dim3(256), 0, s, st, partials, (int)(grid.x * grid.y),
+                         u2_slot);
     }
     prof::end(s);
   }
@@ -532,12 +538,55 @@ struct ProfScope {
   ~ProfScope() { prof::on = saved; }
 };
 
+// U2 of iteration k depends only on S2(k) and on U2(k-1); the next iteration's operator passes do not
+// read what it writes.  So it runs on a second stream (default priority) beside them, filling the
+// memory bandwidth the latency-bound P3 leaves unused.  Ordering: U2(k) after P2(k+1) (hence after
+// S2(k)); P5(k+2) after U2(k) (P5(k+2) overwrites u_k, which U2(k) reads, and S2(k+2) refills U2(k)'s
+// coefficient slot); the main stream joins the last U2 at the end of every batch of iterations.
+// Inside a captured chunk these events become graph edges.
+struct U2Side {
+  int dev = -1;
+  hipStream_t s2 = nullptr;
+  std::vector<hipEvent_t> after_p2, after_u2;
+};
+static thread_local U2Side g_u2_side;
+// Batch workers keep U2 on their own stream: the RVEs already overlap each other, and a second stream
+// per worker would double the streams sharing the process's few hardware queues (measured: the
+// 64-RVE batch went from 2.9 to 3.7 s with side streams).
+static thread_local bool g_u2_inline = false;
+static rve_status u2_side(int count, U2Side** out) {
+  U2Side& U = g_u2_side;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (U.dev != dev) {  // first use on this thread, or the caller moved to another device
+    U.s2 = nullptr;
+    U.after_p2.clear();
+    U.after_u2.clear();
+    HIPCHK(hipStreamCreateWithFlags(&U.s2, hipStreamNonBlocking));
+    U.dev = dev;
+  }
+  while ((int)U.after_p2.size() < count + 1) {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+    U.after_p2.push_back(a);
+    U.after_u2.push_back(b);
+  }
+  *out = &U;
+  return RVE_OK;
+}
+
 // Enqueue `count` MINRES iterations starting from buffer phase (ia, ib, ic, id1, id2); returns the
 // phase after them.  The buffer roles rotate with period 3 (u) and 2 (d).
 template <typename T>
-static void enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, const float* phi, const Material<T>& mat,
-                               const Tables<T>& tb, cx<T>* spec, MinresState* st, double* part, int count, int ph[5],
-                               hipStream_t s) {
+static rve_status enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, const float* phi,
+                                     const Material<T>& mat, const Tables<T>& tb, cx<T>* spec, MinresState* st,
+                                     double* part, int count, int ph[5], hipStream_t s) {
+  U2Side* U = nullptr;
+  rve_status r = u2_side(count, &U);
+  if (r != RVE_OK) return r;
+  // profiled solves keep U2 on the solve stream, so that every launch is timed alone
+  hipStream_t s2 = (prof::on || g_u2_inline) ? s : U->s2;
   const long long n6 = 6 * pl.g.nvox;
   dim3 vg, vb;
   vec_grid(nc, &vg, &vb);
@@ -548,22 +597,46 @@ static void enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, const f
   int& ic = ph[2];
   int& id1 = ph[3];
   int& id2 = ph[4];
-  for (int j = 0; j < count; ++j) {
-    apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s);
-    prof::begin<T>(prof::U2, s);
-    const long long nv = vec ? n6 / Vec16<T>::n : n6;
-    const dim3 ug((unsigned)((nv + kThreads - 1) / kThreads), nc);
+  const long long nv = vec ? n6 / Vec16<T>::n : n6;
+  const dim3 ug((unsigned)((nv + kThreads - 1) / kThreads), nc);
+  // U2 of iteration jj on the second stream, after event `ev` of the main stream
+  auto u2 = [&](int jj, int d2, int d1, int uk, hipEvent_t ev) -> rve_status {
+    HIPCHK(hipStreamWaitEvent(s2, ev, 0));
+    prof::begin<T>(prof::U2, s2);
     if (vec)
-      hipLaunchKernelGGL((k_direction<T, true>), ug, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
+      hipLaunchKernelGGL((k_direction<T, true>), ug, vb, 0, s2, B.d[d2], B.d[d1], B.u[uk], B.x, st, n6, jj & 1);
     else
-      hipLaunchKernelGGL((k_direction<T, false>), ug, vb, 0, s, B.d[id2], B.d[id1], B.u[ib], B.x, st, n6);
-    prof::end(s);
+      hipLaunchKernelGGL((k_direction<T, false>), ug, vb, 0, s2, B.d[d2], B.d[d1], B.u[uk], B.x, st, n6, jj & 1);
+    prof::end(s2);
+    HIPCHK(hipEventRecord(U->after_u2[jj], s2));
+    return RVE_OK;
+  };
+  int prev[3] = {0, 0, 0};  // (d2, d1, uk) buffer indices of the previous iteration
+  for (int j = 0; j < count; ++j) {
+    // iteration j's operator; U2(j-1) starts when P2(j) is done and streams beside P3(j), the pass
+    // that leaves the most bandwidth unused
+    apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s, j & 1,
+                j >= 2 ? U->after_u2[j - 2] : nullptr, j >= 1 ? U->after_p2[j] : nullptr);
+    if (j >= 1) {
+      const rve_status r2 = u2(j - 1, prev[0], prev[1], prev[2], U->after_p2[j]);
+      if (r2 != RVE_OK) return r2;
+    }
+    prev[0] = id2;
+    prev[1] = id1;
+    prev[2] = ib;
     const int t0 = ia;
     ia = ib;
     ib = ic;
     ic = t0;
     std::swap(id1, id2);
   }
+  if (count > 0) {
+    HIPCHK(hipEventRecord(U->after_p2[count], s));  // after the last S2
+    const rve_status r2 = u2(count - 1, prev[0], prev[1], prev[2], U->after_p2[count]);
+    if (r2 != RVE_OK) return r2;
+  }
+  if (count > 0) HIPCHK(hipStreamWaitEvent(s, U->after_u2[count - 1], 0));
+  return RVE_OK;
 }
 
 // A captured chunk of MINRES iterations, replayed until every case has finished.  The key holds every
@@ -608,6 +681,8 @@ static std::vector<unsigned char> chunk_key(const Plan& pl, int nc, const Minres
   put(&chunk, sizeof(chunk));
   const bool po = prof::on;
   put(&po, sizeof(po));
+  const bool inl = g_u2_inline;  // the captured graph has U2 on a side stream or inline
+  put(&inl, sizeof(inl));
   return k;
 }
 
@@ -626,6 +701,11 @@ static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const fl
   std::vector<MinresState> hs(nc);
   ProfScope prof_scope(true);
   const int chunk = ((check + 5) / 6) * 6;
+  {
+    U2Side* U = nullptr;  // the second stream and its events exist before any capture starts
+    const rve_status r = u2_side(std::max(chunk, check), &U);
+    if (r != RVE_OK) return r;
+  }
   ChunkGraph& G = g_chunk_graph[sizeof(T) == 8 ? 1 : 0];
   // per-kernel event timing brackets individual launches: profiled solves launch directly
   bool use_graph = graphs_enabled() && !prof::on;
@@ -640,10 +720,10 @@ static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const fl
       int ph[5] = {0, 1, 2, 0, 1};
       bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
-        enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk, ph, s);
+        const rve_status er = enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk, ph, s);
         const hipError_t le = hipGetLastError();
         hipGraph_t gr = nullptr;
-        ok = hipStreamEndCapture(s, &gr) == hipSuccess && le == hipSuccess && gr != nullptr;
+        ok = hipStreamEndCapture(s, &gr) == hipSuccess && le == hipSuccess && gr != nullptr && er == RVE_OK;
         if (ok) {
           G.graph = gr;
           ok = hipGraphInstantiate(&G.exec, gr, nullptr, nullptr, 0) == hipSuccess;
@@ -673,7 +753,8 @@ static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const fl
       it += chunk;
     } else {
       const int n = std::min(check, max_iter - it);
-      enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, n, ph, s);
+      const rve_status er = enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, n, ph, s);
+      if (er != RVE_OK) return er;
       it += n;
     }
     HIPCHK(hipGetLastError());
@@ -1372,6 +1453,11 @@ rve_status solve_rve_batch(rve_batch_item* items, int32_t n_items, const rve_opt
   if (hipGetDevice(&dev) != hipSuccess) return RVE_EDEVICE;
   auto worker = [&](int w) {
     if (hipSetDevice(dev) != hipSuccess) return;
+    struct Inline {  // restored on exit: worker 0 is the calling thread
+      bool saved = g_u2_inline;
+      Inline() { g_u2_inline = true; }
+      ~Inline() { g_u2_inline = saved; }
+    } inline_u2;
     char* ws = (char*)workspace + slot * w;
     for (;;) {
       const int k = next.fetch_add(1);

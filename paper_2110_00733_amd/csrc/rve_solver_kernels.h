@@ -173,25 +173,41 @@ __global__ void k_minres_alpha(MinresState* st, const double* partials, int np) 
   if (threadIdx.x == 0) alpha_step(S, s);
 }
 
-// S2: beta_{k+1} from the P5 partials, Givens step, convergence test.
-__global__ void k_minres_givens(MinresState* st, const double* partials, int np) {
+// S2: beta_{k+1} from the P5 partials, Givens step, convergence test; the iteration's U2
+// coefficients go to slot `slot` (inactive when the case had already finished).
+__global__ void k_minres_givens(MinresState* st, const double* partials, int np, int slot) {
   __shared__ double red[16];
   const int cs = blockIdx.x;
   MinresState& S = st[cs];
-  if (S.done) return;
+  if (S.done) {
+    if (threadIdx.x == 0) S.u2[slot].active = 0;
+    return;
+  }
   const double s = sum_partials(partials + (long long)cs * np, np, red);
-  if (threadIdx.x == 0) givens_step(S, s);
+  if (threadIdx.x == 0) {
+    givens_step(S, s);
+    U2Coef& u = S.u2[slot];
+    u.cd_u = S.cd_u;
+    u.cd_d1 = S.cd_d1;
+    u.cd_d2 = S.cd_d2;
+    u.cx = S.cx;
+    u.cx_prev = S.cx_prev;
+    u.xmode = S.xmode;
+    u.active = 1;
+  }
 }
 
 // U2: d_k = cd_u u_k + cd_d1 d_{k-1} + cd_d2 d_{k-2} (written over d_{k-2}); x += cx d_k.
 // One 16-byte vector per thread over a grid that covers the field once (a grid-stride loop over a
 // fixed grid streamed about 10% slower); every load of the element is issued before its arithmetic.
+// Coefficients come from the slot S2 filled for this iteration (the live state already belongs to
+// the next iteration when U2 runs beside it).
 template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* uk, T* x, const MinresState* st,
-                                                   long long n6) {
+                                                   long long n6, int slot) {
   const int cs = blockIdx.y;
-  const MinresState& S = st[cs];
-  if (S.done) return;
+  const U2Coef& S = st[cs].u2[slot];
+  if (!S.active) return;
   const T a = (T)S.cd_u, b = (T)S.cd_d1, c = (T)S.cd_d2, xc = (T)S.cx, xp = (T)S.cx_prev;
   const int mode = S.xmode;  // uniform per block (one case)
   const long long off = (long long)cs * n6;
