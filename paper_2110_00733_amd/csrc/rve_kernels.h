@@ -116,8 +116,17 @@ __device__ __forceinline__ long long spec_t_off(const GridDims& g, int n0, int n
 // reductions are deterministic; device-wide fences inside the streaming kernels would write back the
 // whole L2 of every XCD and cost far more than a separate launch)
 __device__ __forceinline__ double sum_partials(const double* p, int np, double* red) {
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += p[i];
+  // eight independent loads in flight per thread (a dependent chain of loads made these single-block
+  // steps latency-bound), combined in a fixed order
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int nt = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 7 * nt < np; i += 8 * nt) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += p[i + u * nt];
+  }
+  for (; i < np; i += nt) a[0] += p[i];
+  const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   return block_sum(acc, red);
 }
 

@@ -545,26 +545,20 @@ struct ProfScope {
 // coefficient slot); the main stream joins the last U2 at the end of every batch of iterations.
 // Inside a captured chunk these events become graph edges.
 struct U2Side {
-  int dev = -1;
   hipStream_t s2 = nullptr;
   std::vector<hipEvent_t> after_p2, after_u2;
 };
-static thread_local U2Side g_u2_side;
+static thread_local std::vector<U2Side> g_u2_side;  // per device, kept for the thread's lifetime
 // Batch workers keep U2 on their own stream: the RVEs already overlap each other, and a second stream
 // per worker would double the streams sharing the process's few hardware queues (measured: the
 // 64-RVE batch went from 2.9 to 3.7 s with side streams).
 static thread_local bool g_u2_inline = false;
 static rve_status u2_side(int count, U2Side** out) {
-  U2Side& U = g_u2_side;
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
-  if (U.dev != dev) {  // first use on this thread, or the caller moved to another device
-    U.s2 = nullptr;
-    U.after_p2.clear();
-    U.after_u2.clear();
-    HIPCHK(hipStreamCreateWithFlags(&U.s2, hipStreamNonBlocking));
-    U.dev = dev;
-  }
+  if ((int)g_u2_side.size() <= dev) g_u2_side.resize(dev + 1);
+  U2Side& U = g_u2_side[dev];
+  if (!U.s2) HIPCHK(hipStreamCreateWithFlags(&U.s2, hipStreamNonBlocking));
   while ((int)U.after_p2.size() < count + 1) {
     hipEvent_t a, b;
     HIPCHK(hipEventCreateWithFlags(&a, hipEventDisableTiming));

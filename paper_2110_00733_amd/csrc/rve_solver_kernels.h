@@ -94,9 +94,7 @@ __global__ void k_accum(double* x64, const Td* d, long long n6, const int* activ
 __global__ void k_sum_partials(const double* partials, int np, double* out, int ostride, int take_sqrt) {
   __shared__ double red[16];
   const int cs = blockIdx.x;
-  double acc = 0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[(long long)cs * np + i];
-  const double s = block_sum(acc, red);
+  const double s = sum_partials(partials + (long long)cs * np, np, red);
   if (threadIdx.x == 0) out[(long long)cs * ostride] = take_sqrt ? sqrt(s) : s;
 }
 
@@ -117,9 +115,7 @@ __global__ void k_minres_init(MinresState* st, const double* partials, int np, C
                               double safety, double inner_floor, int max_iter) {
   __shared__ double red[16];
   const int cs = blockIdx.x;
-  double acc = 0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[(long long)cs * np + i];
-  const double s = block_sum(acc, red);
+  const double s = sum_partials(partials + (long long)cs * np, np, red);
   if (threadIdx.x == 0) {
     MinresState& S = st[cs];
     const double beta = sqrt(s);
