@@ -516,3 +516,26 @@ def test_profiler_separates_precisions_and_counts_iterations():
             assert 1 <= cnt64 < its and ms64 > 0, (k, cnt64)
     rve.profile_reset()
     assert all(v == (0.0, 0) for v in rve.profile_read().values())
+
+
+def test_side_stream_u2_matches_inline():
+    """U2 runs on a second stream beside the next iteration's P3 in a normal solve, and inline on the
+    solve stream when the profiler is on: the arithmetic is the same, so the results must be identical
+    bit for bit (any missing ordering between the streams would show here)."""
+    rve = _rve()
+    n = (64, 64, 64)
+    phi, _ = li.octet_phase_map(n, 0.15)
+    d = _dev(phi)
+    E = np.eye(6)[[0, 3]]
+    side = rve.solve(d, C1, E, tol=1e-7)
+    rve.profile_enable(True)
+    try:
+        inline = rve.solve(d, C1, E, tol=1e-7)
+    finally:
+        rve.profile_enable(False)
+    again = rve.solve(d, C1, E, tol=1e-7)
+    for r in (inline, again):
+        assert r["status"] == 0
+        assert np.array_equal(r["iterations"], side["iterations"])
+        assert np.array_equal(r["eff_stress"], side["eff_stress"])
+        assert torch.equal(r["strain"], side["strain"])
