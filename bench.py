@@ -10,7 +10,7 @@ eps_11 = 1e-3, isotropic solid E = 1, nu = 0.3, empty phase of zero stiffness, t
 
 Prints one JSON line: voxel-iterations/s (value), wall time per solve (ms_per_step), the roofline
 entry of the dominant kernel (HIP-event durations recorded on the solve stream inside the timed
-solves) and the FP64 CPU checker's rate on a bounded sample of the same problem.
+solves) and the FP64 CPU oracle's rate on a bounded sample of the same problem.
 """
 import argparse
 import json
@@ -154,8 +154,8 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build's solver runs on a single MI355X "
-              "(see DESIGN.md for how the path would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver runs each RVE on a single MI355X (load cases and "
+              "RVEs are independent solves; a multi-GPU run would split them); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -271,11 +271,18 @@ def main():
         cpu = {"value": nvox * args.cpu_iters / secs, "unit": "voxel-iterations/s", "cores": oracle.num_threads(),
                "kind": "oracle",
                "sample": f"{args.cpu_iters} FP64 MINRES iteration(s) (operator apply + vector updates) of the CPU "
-                         f"checker on the same {n[0]}x{n[1]}x{n[2]} problem, zero start; {secs:.1f} s"}
+                         f"oracle on the same {n[0]}x{n[1]}x{n[2]} problem, zero start; {secs:.1f} s"}
         log(f"cpu baseline {cpu['value']:.3e} voxel-it/s in {time.time() - t1:.1f}s wall")
 
+    # whole-solve average: the MINRES iterations' algorithmic bytes over the timed wall time, which
+    # also holds the setup, the FP64 refinement applies and the post-processing (so a lower bound)
+    iter_kinds = ("P1_stiffness_fft_axis2_alpha", "P2_fft_axis1", "P3_fft_axis0_projection", "P4_ifft_axis1",
+                  "P5_ifft_axis2_lanczos", "U2_direction_update")
+    iter_bytes = sum(algorithmic_bytes(k, n, 1, elem) for k in iter_kinds)
+    solve_gbs = iter_bytes * sum(iters) / total_t / 1e9
     cfg.update({"iterations_per_solve": iters[-1] // nc if nc else 0, "rel_residual": max(res),
                 "wall_time_to_tol_ms": round(ms_per_step, 2), "minres_iterations_per_s": sum(iters) / total_t / nc,
+                "solve_avg_hbm_gbs": round(solve_gbs, 1), "solve_avg_hbm_frac": round(solve_gbs / HBM_PEAK_GBS, 4),
                 "parallelism": "single-gpu"})
     line = {"metric": "voxel-iterations/s + wall time to 1e-6 residual at 256^3, learned vs plain",
             "value": value, "unit": "voxel-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

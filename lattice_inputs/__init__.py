@@ -1,9 +1,9 @@
-"""Seeded synthetic inputs for the lattice homogenization solver and its CPU checker.
+"""Seeded synthetic inputs for the lattice homogenization solver and its CPU oracle.
 
 Octet-truss voxel phase maps (Voigt fine-grid fractions, plain voxelization as S=1), manufacturing
 defects (roughness + pores), simple analytic patterns (laminates, inclusions) and the macro strain
 load cases.  Nothing here performs any step of the homogenization method itself; both the GPU path
-and the FP64 checker only read what this module produces.
+and the FP64 oracle only read what this module produces.
 
 Geometry: the octet truss of the section "Lattice geometry and simulation parameters" (all 24 FCC
 nearest-neighbour struts of the cubic cell, capsules of radius r); voxel fractions by the Voigt

@@ -2,7 +2,7 @@
  * Seeded synthetic inputs for lattice homogenization: octet-truss phase maps.
  *
  * This module only builds INPUTS (voxel solid-fraction maps phi in [0,1]). It holds none of the
- * homogenization arithmetic, so both the FP64 CPU checker and the GPU solver can consume its output.
+ * homogenization arithmetic, so both the FP64 CPU oracle and the GPU solver can consume its output.
  *
  * Geometry (Sec. "Lattice geometry and simulation parameters"): octet truss = all nearest-neighbour
  * bonds of the FCC lattice, 24 struts per cubic cell, each strut a capsule (cylinder with spherical

@@ -1,9 +1,9 @@
-"""FP64 CPU checker for the Galerkin-FFT homogenization solver.
+"""FP64 CPU oracle for the Galerkin-FFT homogenization solver.
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU-baseline leg of the
 benchmark, never by the solver package.  The arithmetic lives in ``galerkin_oracle.c`` (plain C,
 FP64, OpenMP over FFT lines); this module converts between the Mandel vectors used at the solver's
-interface and the Cartesian tensor components used inside the checker.
+interface and the Cartesian tensor components used inside the oracle.
 
 Paper sections followed: "Galerkin-FFT with discrete differences and mixed loading control"
 (eqs. freq, galop, gallin, linearOp, galres, freqrot) and "Voigt approaches" (C = phi C_m).

@@ -1,5 +1,5 @@
 /*
- * FP64 CPU checker ("oracle") for the Galerkin-FFT homogenization of lattices with empty phases.
+ * FP64 CPU oracle for the Galerkin-FFT homogenization of lattices with empty phases.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline leg of the
  * benchmark may load this library.  It shares no code, header, table or constant with the GPU

@@ -1,4 +1,4 @@
-"""Dense brute-force references for tiny grids (numpy only; independent of the FFT checker).
+"""Dense brute-force references for tiny grids (numpy only; independent of the FFT oracle).
 
 The rotated forward-difference scheme of eq. (freqrot) is, in real space, the "8-corner" stencil:
 the centre strain of voxel v is built from periodic nodal displacements u at the 8 voxel corners,

@@ -1,7 +1,7 @@
 import os
 import sys
 
-# The CPU checker's OpenMP threads must not spin between parallel regions: the tests interleave it
+# The CPU oracle's OpenMP threads must not spin between parallel regions: the tests interleave it
 # with numpy's own BLAS threads, and spinning workers starve them.
 os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
 

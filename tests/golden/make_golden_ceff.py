@@ -1,7 +1,7 @@
 """Write oracle-only effective stiffness goldens for ideal octet lattices.
 
-Calls only the FP64 CPU checker (oracle/) and the seeded input generator (lattice_inputs/).  The
-ideal octet is exactly cubic-symmetric on the voxel grid (checked by the CPU tests), so the checker
+Calls only the FP64 CPU oracle (oracle/) and the seeded input generator (lattice_inputs/).  The
+ideal octet is exactly cubic-symmetric on the voxel grid (checked by the CPU tests), so the oracle
 solves the two independent unit load cases e_11 and sqrt2*e_23 and the 6x6 Mandel matrix is assembled
 from C11, C12, C44.  Material: isotropic E = 1, nu = 0.3, empty phase of zero stiffness; 4^3
 sub-voxel Voigt fractions; rotated scheme, natural Nyquist reading; MINRES to tol 1e-10.

@@ -1,9 +1,9 @@
-"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU checker.
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
 
-Tolerances: FP64 kernels agree with the checker to ~1e-12 relative; FP32 kernels to a few
+Tolerances: FP64 kernels agree with the oracle to ~1e-12 relative; FP32 kernels to a few
 units of u32 * log2(N) (u32 = 6e-8), written below as 2e-5 relative to the field maximum.
-Solves: FP64 iterations within 1 of the checker and <sigma> within 1e-9; FP32-mixed C_eff within
-1e-5 relative (Frobenius) of the checker's FP64 C_eff.
+Solves: FP64 iterations within 1 of the oracle and <sigma> within 1e-9; FP32-mixed C_eff within
+1e-5 relative (Frobenius) of the oracle's FP64 C_eff.
 """
 import numpy as np
 import pytest

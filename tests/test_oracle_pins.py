@@ -1,8 +1,8 @@
-"""Pins of the FP64 CPU checker against facts fixed by the paper and by mathematics (no GPU).
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by mathematics (no GPU).
 
-Each test targets a distinct way the checker could be wrong:
+Each test targets a distinct way the oracle could be wrong:
   - DFT/FFT: naive DFT vs closed forms (delta, pure tones, Parseval); FFT vs naive DFT.
-  - Frequencies/projection (eqs. freq, galop, freqrot): the checker's projection must be exactly the
+  - Frequencies/projection (eqs. freq, galop, freqrot): the oracle's projection must be exactly the
     orthogonal projector onto the real-space 8-corner stencil strains (dense SVD, no FFT); invariants.
   - Operator + stiffness: plane-wave eigenvalues 2mu, 2mu, lambda+2mu of Ghat C on a homogeneous solid.
   - Solve (eq. gallin with MINRES): dense minimum-norm solve on tiny grids with voids; laminate closed
