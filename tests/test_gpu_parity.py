@@ -539,3 +539,34 @@ def test_side_stream_u2_matches_inline():
         assert np.array_equal(r["iterations"], side["iterations"])
         assert np.array_equal(r["eff_stress"], side["eff_stress"])
         assert torch.equal(r["strain"], side["strain"])
+
+
+def test_solve_on_null_stream_matches():
+    """solve_rve on the NULL stream (no graph capture there: direct launches, U2 still on the side
+    stream, ordered by events) gives the same result as the captured solve on a stream."""
+    import ctypes
+    rve = _rve()
+    n = (32, 32, 32)
+    phi, _ = li.octet_phase_map(n, 0.10)
+    d = _dev(phi)
+    E = np.ascontiguousarray(li.uniaxial_strain(1e-3)[None])
+    ref = rve.solve(d, C1, E, tol=1e-7)
+    lib = rve.load_library()
+    g = rve.make_grid(n)
+    opt = rve.default_options(tol=1e-7)
+    C = np.ascontiguousarray(np.stack([np.zeros((6, 6)), C1]).reshape(2, 36))
+    nbytes = lib.rve_workspace_bytes(ctypes.byref(g), 1, ctypes.byref(opt))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    strain = torch.empty((1, 6) + n, dtype=torch.float32, device="cuda")
+    eff, its, res = np.zeros((1, 6)), np.zeros(1, dtype=np.int32), np.zeros(1)
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    torch.cuda.synchronize()
+    st = lib.solve_rve(ctypes.byref(g), ctypes.c_void_p(d.data_ptr()), dp(C), dp(E), 1, ctypes.byref(opt), None,
+                       ctypes.c_void_p(strain.data_ptr()), None, dp(eff),
+                       its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), dp(res), ctypes.c_void_p(ws.data_ptr()),
+                       ctypes.c_size_t(nbytes), None)
+    torch.cuda.synchronize()
+    assert st == 0
+    assert np.array_equal(its, ref["iterations"])
+    assert np.array_equal(eff, ref["eff_stress"])
+    assert torch.equal(strain, ref["strain"])
