@@ -179,7 +179,8 @@ int32_t rve_profile_read(double* total_ms, int64_t* launches, int32_t max_kinds)
 const char* rve_profile_kind_name(int32_t kind);
 
 /* Autotuner.  Times the operator apply for each registered factorisation N = NA * NB of every axis
- * length (e.g. 64 = 8*8 or 16*4, 96 = 12*8 or 16*6), the P3 component split (whole / halves) and every
+ * length (e.g. 64 = 8*8 or 16*4, 96 = 12*8 or 16*6), the P3 component split (whole / halves, and
+ * for FP64 also thirds) and every
  * admissible tile width of each pass kind (P3 pencils per block, P2/P4 rows per block, P1/P5 rows
  * per block; coordinate descent, HIP events on
  * hip_stream, 3 repetitions each) for this grid and precision, using the caller's workspace (at least
@@ -196,7 +197,8 @@ int32_t rve_load_tuning(const char* path);
 
 /* Tiles the next call on this grid and precision will use: tiles7 = {P1/P5 rows, P3 pencils,
  * P2/P4 rows, P3 component split in effect (1: six components per thread, 2: three per thread over
- * two block halves; the split needs each half to be whole 64-lane waves), then for axes 0, 1, 2 the
+ * two block halves, each whole 64-lane waves; 3: two per thread over three one-wave groups, which
+ * needs NB of axis 0 to divide 64), then for axes 0, 1, 2 the
  * first-stage radix NA of the factorisation N = NA * NB in use}.  Returns 1 if they come from the
  * tuner, 0 if they are the built-in heuristic. */
 int32_t rve_tuned_tiles(const rve_grid* grid, int32_t precision, int32_t* tiles7);

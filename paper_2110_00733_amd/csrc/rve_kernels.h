@@ -712,6 +712,177 @@ __global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__
   }
 }
 
+// Projection step of the three-group P3 for group G (a compile-time constant, so that every register
+// slot index is one).  Entry e is projected by group e % 3.  The value a non-owner group sends for
+// entry e of lane q sits at slot (2 e + k) WNB + q, k = 0 for the group after the owner (mod 3), 1 for
+// the one before; after the exchange D[r][3m + j] holds component 2j + r of the group's entry 3m + G
+// (j = 0..2), and the projected values go back the same way.  Every group passes the same barriers.
+template <typename T, int NA, int NB, int E, int G>
+__device__ __forceinline__ void split3_project(cx<T> (&D)[2][E], cx<T>* lds_all, int WNB, int q, int t,
+                                               const FreqTables<T>& ft, T c1c2, T s1c2, T c1s2, T inv_total) {
+  constexpr int TT = NB;
+  constexpr int CB = (NA + TT - 1) / TT;
+  constexpr int GA = (G + 1) % 3, GB = (G + 2) % 3;  // the groups after and before G
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    lds_barrier();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int o = e % 3;
+      if (o != G) lds_all[(e * 2 + (G == (o + 1) % 3 ? 0 : 1)) * WNB + q] = D[r][e];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int m = 0; m < E / 3; ++m) {
+      const int e = 3 * m + G;
+      D[r][3 * m + GA] = lds_all[(e * 2 + 0) * WNB + q];
+      D[r][3 * m + GB] = lds_all[(e * 2 + 1) * WNB + q];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int a = t + TT * j;
+    if (a < NA) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int e = j * NB + b;
+        if (e % 3 != G) continue;
+        const int k0 = a + NA * b;
+        const T s0 = ft.s[0][k0], c0 = ft.c[0][k0];
+        const T w0 = s0 * c1c2, w1 = c0 * s1c2, w2 = c0 * c1s2;
+        const int m3 = e - G;
+        project_mandel(D[0][m3], D[1][m3], D[0][m3 + 1], D[1][m3 + 1], D[0][m3 + 2], D[1][m3 + 2], w0, w1, w2,
+                       inv_total);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    lds_barrier();
+#pragma unroll
+    for (int m = 0; m < E / 3; ++m) {
+      const int e = 3 * m + G;
+      lds_all[(e * 2 + 0) * WNB + q] = D[r][3 * m + GA];
+      lds_all[(e * 2 + 1) * WNB + q] = D[r][3 * m + GB];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int o = e % 3;
+      if (o != G) D[r][e] = lds_all[(e * 2 + (G == (o + 1) % 3 ? 0 : 1)) * WNB + q];
+    }
+  }
+}
+
+// P3 with the six components split over three groups of the block (group g owns components 2g and
+// 2g+1): a third of the whole-pencil registers, which keeps the FP64 transform out of scratch.
+// Each group is one wave (W*NB = 64).  grid (ceil(N1/W), K2, ncases), block 3*W*NB threads, dyn. LDS
+// max(3*NA*(NB*W+1), 2*E*NB*W) complex (one transform exchange area per group, reused for the
+// projection exchange).
+template <typename T, int NA, int NB, bool IDENT>
+__global__ __launch_bounds__(192) void k_axis0_project_split3(cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw,
+                                                              FreqTables<T> ft, GridDims g, int W, T inv_total,
+                                                              const MinresState* __restrict__ st) {
+  constexpr int N = NA * NB;
+  constexpr int TT = NB;
+  constexpr int CB = (NA + TT - 1) / TT;
+  constexpr int E0 = (NA > CB * NB) ? NA : CB * NB;
+  constexpr int E = (E0 + 2) / 3 * 3;  // the host sizes LDS for max(3 NA (NB W + 1), 2 E NB W) complex
+  extern __shared__ unsigned char smem_raw[];
+  const int cs = blockIdx.z;
+  if (st && st[cs].finish) return;
+  const int k2 = g.k2 - 1 - (int)blockIdx.y;  // descending, as the other P3 variants
+  const int tid = threadIdx.x;
+  const int WNB = W * NB;  // 64: the group index is wave-uniform
+  const int q = tid % WNB, grp = __builtin_amdgcn_readfirstlane(tid / WNB);
+  const int t = q % NB, w = q / NB;
+  const int k1 = blockIdx.x * W + w;
+  const bool ok = k1 < g.n1;
+  const int RS = NB * W + 1;
+  cx<T>* lds_all = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* lds = lds_all + grp * NA * RS;
+  const long long pstride = (long long)g.n0 * g.n1;
+  cx<T>* base = spec + spec_t_plane(g, cs, k2, 2 * grp) + spec_t_off(g, 0, ok ? k1 : 0);
+  const long long toff = spec_t_off(g, t, 0);  // element t + NB i at toff + i NB n1 (tile divides NB)
+
+  cx<T> D[2][E];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) D[c][i] = ok ? base[c * pstride + toff + (long long)i * (NB * g.n1)] : mk<T>(0, 0);
+#pragma unroll
+    for (int i = NA; i < E; ++i) D[c][i] = mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    DFT<NA, -1, T>::run(D[c]);
+#pragma unroll
+    for (int a = 1; a < NA; ++a) D[c][a] = cmul(D[c][a], tw[(t * a) % N]);
+    lds_barrier();
+#pragma unroll
+    for (int a = 0; a < NA; ++a) lds[a * RS + w * NB + t] = D[c][a];
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) D[c][j * NB + u] = lds[a * RS + w * NB + u];
+        DFT<NB, -1, T>::run(&D[c][j * NB]);
+      }
+    }
+  }
+
+  const int k1c = ok ? k1 : 0;
+  const T s1 = ft.s[1][k1c], c1 = ft.c[1][k1c], s2 = ft.s[2][k2], c2 = ft.c[2][k2];
+  const T c1c2 = c1 * c2, s1c2 = s1 * c2, c1s2 = c1 * s2;
+  if (IDENT) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < E; ++e) D[c][e] = scl(D[c][e], inv_total);
+  } else if (grp == 0) {
+    split3_project<T, NA, NB, E, 0>(D, lds_all, WNB, q, t, ft, c1c2, s1c2, c1s2, inv_total);
+  } else if (grp == 1) {
+    split3_project<T, NA, NB, E, 1>(D, lds_all, WNB, q, t, ft, c1c2, s1c2, c1s2, inv_total);
+  } else {
+    split3_project<T, NA, NB, E, 2>(D, lds_all, WNB, q, t, ft, c1c2, s1c2, c1s2, inv_total);
+  }
+
+  // ---- inverse along axis 0
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+        DFT<NB, 1, T>::run(&D[c][j * NB]);
+        if (a > 0) {
+#pragma unroll
+          for (int u = 1; u < NB; ++u) D[c][j * NB + u] = cmulc(D[c][j * NB + u], tw[(u * a) % N]);
+        }
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int a = t + TT * j;
+      if (a < NA) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) lds[a * RS + w * NB + u] = D[c][j * NB + u];
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int a = 0; a < NA; ++a) D[c][a] = lds[a * RS + w * NB + t];
+    DFT<NA, 1, T>::run(D[c]);
+    if (ok) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) base[c * pstride + toff + (long long)i * (NB * g.n1)] = D[c][i];
+    }
+  }
+}
+
 // ============================================================================ P5
 // grid (ceil(N1/W), N0, ncases), block W*NB threads, dyn. LDS W*max(NA*(NB+1), N+1) complex
 // Lanczos mode (uk != nullptr, MINRES iterations): the transform output p = A v_k is never stored;

@@ -21,6 +21,7 @@ struct LenKernels {
   P2Fn<T> p2f, p2i;
   P3Fn<T> p3, p3_ident;
   P3Fn<T> p3s, p3s_ident;  // components split over two halves of the block
+  P3Fn<T> p3t, p3t_ident;  // components split over three groups of the block
   P5Fn<T> p5;
 };
 
@@ -45,6 +46,7 @@ const LenEntry* find_len(int n, int variant = 0);
   {&rve::k_fwd_axis2<T_, NA_, NB_>, &rve::k_axis1<T_, NA_, NB_, -1>, &rve::k_axis1<T_, NA_, NB_, 1>, \
    &rve::k_axis0_project<T_, NA_, NB_, false>, &rve::k_axis0_project<T_, NA_, NB_, true>,              \
    &rve::k_axis0_project_split<T_, NA_, NB_, false>, &rve::k_axis0_project_split<T_, NA_, NB_, true>,  \
+   &rve::k_axis0_project_split3<T_, NA_, NB_, false>, &rve::k_axis0_project_split3<T_, NA_, NB_, true>, \
    &rve::k_inv_axis2<T_, NA_, NB_>}
 #define RVE_LEN_ENTRY(N_, NA_, NB_) \
   rve::LenEntry { N_, NA_, NB_, RVE_LEN_KERNELS(float, NA_, NB_), RVE_LEN_KERNELS(double, NA_, NB_) }

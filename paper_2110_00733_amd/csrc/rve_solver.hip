@@ -139,7 +139,8 @@ static long long align_up(long long v, long long a) { return (v + a - 1) / a * a
 
 struct Tiles {
   int W1, W3, R2;       // P1/P5 row tile, P3 pencil tile, P2/P4 rows per block
-  int S3 = 2;           // P3 component split: 1 = all six per thread, 2 = three per thread (two block halves)
+  int S3 = 2;           // P3 component split: 1 = all six per thread, 2 = three per thread (two block halves),
+                        // 3 = two per thread (three one-wave groups)
   int F[3] = {0, 0, 0};  // factorisation (registry variant) of each axis length
 };
 struct Plan {
@@ -196,18 +197,31 @@ static int tile_p1(const Plan& pl, int elem) {
   return W;
 }
 // P3 may use the device's whole per-block LDS (160 KiB on gfx950): the split kernel's two exchange
-// areas need just over 64 KiB for 16 pencils of 256, i.e. 128-byte row segments.
+// areas need just over 64 KiB for 16 pencils of 256 (the tuner usually takes 4-8 on the tiled copy).
 static int tile_p3_for(const Plan& pl, int elem, int sp) {
   const int na = axis(pl, elem, 0)->na, nb = axis(pl, elem, 0)->nb;
+  if (sp == 3) return 64 / nb;  // one wave per component group
   int W = pl.t[elem == 8].W3;
   while (W > 1 && (W * nb > 256 || sp * 2LL * elem * na * (nb * W + 1) > pl.lds_cap3)) W /= 2;
   return W;
 }
-// The split variant needs each block half (W*NB threads) to be whole waves; otherwise whole pencils.
+// LDS (complex elements) of the three-group P3 at tile W: the larger of its three transform exchange
+// areas and its projection exchange.
+static long long lds_p3_split3(int na, int nb, int W) {
+  const int cb = (na + nb - 1) / nb;
+  const int e0 = std::max(na, cb * nb), e = (e0 + 2) / 3 * 3;
+  return std::max(3LL * na * (nb * W + 1), 2LL * e * nb * W);
+}
+// The split variants need each block part (W*NB threads) to be whole waves; otherwise whole pencils.
+// A three-group request falls back to halves (then whole pencils) where NB does not divide 64 or the
+// LDS does not fit.
 static int split_p3(const Plan& pl, int elem) {
-  if (pl.t[elem == 8].S3 == 1) return 1;
+  const int req = pl.t[elem == 8].S3;
+  if (req == 1) return 1;
+  const int na = axis(pl, elem, 0)->na, nb = axis(pl, elem, 0)->nb;
+  if (req == 3 && 64 % nb == 0 && 2LL * elem * lds_p3_split3(na, nb, 64 / nb) <= pl.lds_cap3) return 3;
   const int W = tile_p3_for(pl, elem, 2);
-  return (W * axis(pl, elem, 0)->nb) % 64 == 0 ? 2 : 1;
+  return (W * nb) % 64 == 0 ? 2 : 1;
 }
 static int tile_p3(const Plan& pl, int elem) { return tile_p3_for(pl, elem, split_p3(pl, elem)); }
 static int rows_p2(const Plan& pl, int elem) {
@@ -475,7 +489,7 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
   {
     const int W = tile_p3(pl, elem);
     const int sp = split_p3(pl, elem);
-    const size_t lds = sizeof(cx<T>) * sp * na0 * (nb0 * W + 1);
+    const size_t lds = sizeof(cx<T>) * (sp == 3 ? lds_p3_split3(na0, nb0, W) : (long long)sp * na0 * (nb0 * W + 1));
     FreqTables<T> ft;
     for (int p = 0; p < 3; ++p) {
       ft.s[p] = tb.s[p];
@@ -483,7 +497,9 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     }
     dim3 grid((g.n1 + W - 1) / W, g.k2, nc);
     prof::begin<T>(prof::P3, s);
-    const P3Fn<T> fn = sp == 2 ? (identity ? K0.p3s_ident : K0.p3s) : (identity ? K0.p3_ident : K0.p3);
+    const P3Fn<T> fn = sp == 3   ? (identity ? K0.p3t_ident : K0.p3t)
+                       : sp == 2 ? (identity ? K0.p3s_ident : K0.p3s)
+                                 : (identity ? K0.p3_ident : K0.p3);
     hipLaunchKernelGGL(fn, grid, dim3(sp * W * nb0), lds, s, spec_t, tb.tw[0], ft, g, W, (T)(1.0 / (double)g.nvox),
                        st);
     prof::end(s);
@@ -871,7 +887,8 @@ extern "C" int32_t rve_load_tuning(const char* path) {
         (k.elem == 4 || k.elem == 8) && t.W1 >= 1 && t.W3 >= 1 && t.R2 >= 1 && t.W1 <= 256 && t.W3 <= 256 &&
         t.R2 <= 256) {
       const char* sp = strstr(line, "\"S3\":");
-      t.S3 = (sp && atoi(sp + 5) == 1) ? 1 : 2;  // absent (older tables): the default
+      const int s3 = sp ? atoi(sp + 5) : 2;
+      t.S3 = (s3 == 1 || s3 == 3) ? s3 : 2;  // absent (older tables): the default
       const char* fp = strstr(line, "\"F\":[");
       int f0 = 0, f1 = 0, f2 = 0;
       if (fp && sscanf(fp, "\"F\":[%d,%d,%d]", &f0, &f1, &f2) == 3 && f0 >= 0 && f1 >= 0 && f2 >= 0 && f0 < 16 &&
@@ -952,20 +969,27 @@ static rve_status autotune_impl(Plan& pl, const rve_grid* grid, int nc, const La
     cur.F[p] = bestv;
     select_axes(&pl);
   }
-  // P3 component split (whole / halves), at the current tiles
+  // P3 component split (whole / halves / thirds), at the current tiles.  Thirds only for FP64, where
+  // they keep the transform out of scratch: in FP32 the plain apply timed here favours them by a hair,
+  // but in the MINRES loop, where U2 streams beside P3, the halves are faster (557 vs 576 ms at 256^3).
   {
     const int keep = cur.S3;
-    cur.S3 = keep == 1 ? 2 : 1;
-    double ms = 0;
-    r = time_apply(&ms);
-    if (r != RVE_OK) {
-      cur.S3 = keep;
-      return r;
+    int bestv = keep;
+    for (int v = 1; v <= (elem == 8 ? 3 : 2); ++v) {
+      if (v == keep) continue;
+      cur.S3 = v;
+      double ms = 0;
+      r = time_apply(&ms);
+      if (r != RVE_OK) {
+        cur.S3 = keep;
+        return r;
+      }
+      if (ms < bms) {
+        bms = ms;
+        bestv = v;
+      }
     }
-    if (ms < bms)
-      bms = ms;
-    else
-      cur.S3 = keep;
+    cur.S3 = bestv;
   }
   const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
   // coordinate descent over the three tiles (P3 pencils, P2/P4 rows, P1/P5 rows)
