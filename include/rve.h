@@ -183,7 +183,7 @@ const char* rve_profile_kind_name(int32_t kind);
  * for FP64 also thirds) and every
  * admissible tile width of each pass kind (P3 pencils per block, P2/P4 rows per block, P1/P5 rows
  * per block; coordinate descent, HIP events on
- * hip_stream, 3 repetitions each) for this grid and precision, using the caller's workspace (at least
+ * hip_stream, 10 repetitions each) for this grid and precision, using the caller's workspace (at least
  * rve_workspace_bytes(grid, n_cases, default options of that precision)).  The fastest tiles are kept
  * in a process-wide table used by every later solve_rve / rve_apply on the same grid and precision,
  * and, if cache_path is non-NULL, the whole table is written there (one JSON object per line).

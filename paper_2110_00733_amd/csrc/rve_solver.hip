@@ -926,7 +926,7 @@ static rve_status autotune_impl(Plan& pl, const rve_grid* grid, int nc, const La
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  const int reps = 3;
+  const int reps = 10;  // three gave tile choices that flipped between runs
   auto time_apply = [&](double* ms) -> rve_status {
     apply_op<T>(pl, nc, x, nullptr, nullptr, id, tb, spec, y, nullptr, nullptr, nullptr, nullptr, 0, s);
     HIPCHK(hipEventRecord(e0, s));
