@@ -51,6 +51,7 @@ void register_group_d();
 void register_group_e();
 void register_group_f();
 void register_group_g();
+void register_group_h();
 extern "C" int32_t rve_load_tuning(const char* path);
 static void ensure_registry() {
   static std::once_flag once;
@@ -62,6 +63,7 @@ static void ensure_registry() {
     register_group_e();
     register_group_f();
     register_group_g();
+    register_group_h();
     const char* f = getenv("RVE_TUNE_FILE");
     if (f && f[0]) rve_load_tuning(f);
   });

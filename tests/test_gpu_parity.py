@@ -459,7 +459,8 @@ def test_stiffness_isotropic_fast_path_and_general_path(which, dt):
 
 
 # registered factorisations N = NA * NB per length, in registry order (variant 0 = default)
-FACTORISATIONS = {16: [4, 8], 24: [6, 8, 12], 32: [8, 16], 48: [12, 8, 16], 64: [8, 16], 96: [12, 16]}
+FACTORISATIONS = {16: [4, 8], 24: [6, 8, 12], 32: [8, 16], 48: [12, 8, 16], 64: [8, 16], 96: [12, 16],
+                  54: [9, 18], 108: [12, 27, 18], 162: [18, 27], 216: [18, 27, 24]}
 
 
 @pytest.mark.parametrize("N", sorted(FACTORISATIONS))
