@@ -927,12 +927,11 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
         sp[c][l] = (n1s < g.n1 && k < g.k2) ? spec[spec_idx(g, cs, k, c, n0, n1s)] : mk<T>(0, 0);
     }
   };
-  gather_pair(0);
-#pragma unroll
-  for (int pr = 0; pr < 3; ++pr) {
-    if (pr < 2) gather_pair(pr + 1);
-    // Lanczos operands for this pair (combination c u_k + c' u_{k-1}), fetched early
-    T dv[CB][NB][2];
+  // Lanczos operands (combination c u_k + c' u_{k-1}) of a pair, fetched early: in FP32 one pair
+  // ahead (the registers are there at two waves per SIMD), in FP64 at the start of the pair
+  constexpr bool DV_AHEAD = sizeof(T) == 4;
+  T dvs[3][CB][NB][2];
+  auto load_dv = [&](int p2) {
     if (lz && row_ok) {
 #pragma unroll
       for (int j = 0; j < CB; ++j) {
@@ -942,12 +941,24 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
           const long long o = row + a + NA * b;
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            const long long oo = (2 * pr + h) * g.nvox + o;
-            dv[j][b][h] = (CB == 1 || a < NA) ? cv * uc[oo] + cvp * umc[oo] : (T)0;
+            const long long oo = (2 * p2 + h) * g.nvox + o;
+            dvs[p2][j][b][h] = (CB == 1 || a < NA) ? cv * uc[oo] + cvp * umc[oo] : (T)0;
           }
         }
       }
     }
+  };
+  if (DV_AHEAD) load_dv(0);
+  gather_pair(0);
+#pragma unroll
+  for (int pr = 0; pr < 3; ++pr) {
+    if (pr < 2) gather_pair(pr + 1);
+    if (DV_AHEAD) {
+      if (pr < 2) load_dv(pr + 1);
+    } else {
+      load_dv(pr);
+    }
+    T (&dv)[CB][NB][2] = dvs[pr];
     lds_barrier();
     if (n1s < g.n1) {
 #pragma unroll
