@@ -82,6 +82,13 @@ struct Material {
   T lam_d, mu2_d, lam_0, mu2_0;
 };
 
+// x when A, else y (references of possibly different types, chosen at compile time)
+template <bool A, typename X, typename Y>
+__device__ __forceinline__ auto& pick(X& x, Y& y) {
+  if constexpr (A) return x;
+  else return y;
+}
+
 // sigma_a = (C e)_a for one voxel, general 6x6 or isotropic form
 template <typename T>
 __device__ __forceinline__ T stiff_row(const T* C, int iso, T lam, T mu2, int a, const T (&e)[6], T tr) {
@@ -927,10 +934,12 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
         sp[c][l] = (n1s < g.n1 && k < g.k2) ? spec[spec_idx(g, cs, k, c, n0, n1s)] : mk<T>(0, 0);
     }
   };
-  // Lanczos operands (combination c u_k + c' u_{k-1}) of a pair, fetched early: in FP32 one pair
-  // ahead (the registers are there at two waves per SIMD), in FP64 at the start of the pair
-  constexpr bool DV_AHEAD = sizeof(T) == 4;
-  T dvs[3][CB][NB][2];
+  // Lanczos operands (combination c u_k + c' u_{k-1}) of a pair, fetched early: one pair ahead in
+  // FP32 where the CB*NB*2 extra registers leave the waves per SIMD unchanged (NA >= 15: the kernel
+  // holds two waves per SIMD either way, at 200-250 VGPRs), else at the start of the pair (smaller NA
+  // would drop from four or three waves per SIMD, larger CB*NB to one; FP64 gains nothing)
+  constexpr bool DV_AHEAD = sizeof(T) == 4 && NA >= 15 && CB * NB <= 16;
+  T dvs[DV_AHEAD ? 3 : 1][CB][NB][2];
   auto load_dv = [&](int p2) {
     if (lz && row_ok) {
 #pragma unroll
@@ -942,23 +951,38 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const long long oo = (2 * p2 + h) * g.nvox + o;
-            dvs[p2][j][b][h] = (CB == 1 || a < NA) ? cv * uc[oo] + cvp * umc[oo] : (T)0;
+            dvs[DV_AHEAD ? p2 : 0][j][b][h] = (CB == 1 || a < NA) ? cv * uc[oo] + cvp * umc[oo] : (T)0;
           }
         }
       }
     }
   };
-  if (DV_AHEAD) load_dv(0);
+  if constexpr (DV_AHEAD) load_dv(0);
   gather_pair(0);
 #pragma unroll
   for (int pr = 0; pr < 3; ++pr) {
     if (pr < 2) gather_pair(pr + 1);
-    if (DV_AHEAD) {
+    T dvl[DV_AHEAD ? 1 : CB][NB][2];
+    if constexpr (DV_AHEAD) {
       if (pr < 2) load_dv(pr + 1);
     } else {
-      load_dv(pr);
+      if (lz && row_ok) {
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          const int a = t + TT * j;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const long long o = row + a + NA * b;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const long long oo = (2 * pr + h) * g.nvox + o;
+              dvl[j][b][h] = (CB == 1 || a < NA) ? cv * uc[oo] + cvp * umc[oo] : (T)0;
+            }
+          }
+        }
+      }
     }
-    T (&dv)[CB][NB][2] = dvs[pr];
+    auto& dv = pick<DV_AHEAD>(dvs[DV_AHEAD ? pr : 0], dvl);
     lds_barrier();
     if (n1s < g.n1) {
 #pragma unroll
