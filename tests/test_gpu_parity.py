@@ -178,6 +178,23 @@ def test_solve_matches_oracle_octet54():
     assert _rel(out32["eff_stress"][0], ref["sigma_mean"]) < 1e-5
 
 
+@pytest.mark.parametrize("n2", [15, 75, 225])
+def test_fp32_mixed_solve_axis2_radix15(n2):
+    """FP32-mixed MINRES with axis-2 lengths 15, 75 and 225 (factorisations 15x1, 15x5, 15x15): the
+    last pass of these transforms fetches the Lanczos operands one component pair ahead, which only
+    a MINRES iteration exercises.  Random two-phase map with a soft second phase, uniaxial strain,
+    tol 1e-8; <sigma> and the strain field against the FP64 oracle."""
+    rve = _rve()
+    n = (12, 10, n2)
+    phi = li.random_phi(n, 31 + n2, 0.3)
+    E = li.uniaxial_strain(1e-3)
+    ref = oracle.solve(n, phi, C1, E, tol=1e-8, maxit=3000, C0=C_SOFT, want_sigma=False)
+    out = rve.solve(_dev(phi), C1, E[None], C_void=C_SOFT, tol=1e-8, max_iter=3000, want_stress=False)
+    assert out["status"] == 0 and out["rel_residual"][0] <= 1e-8
+    assert _rel(out["eff_stress"][0], ref["sigma_mean"]) < 1e-6
+    assert _rel(out["strain"].cpu().numpy()[0], ref["eps"]) < 1e-6
+
+
 def _ceff_golden(n, rho):
     import json
     import os
