@@ -77,8 +77,8 @@ def algorithmic_bytes(kind, n, nc, elem):
         "P3_fft_axis0_projection": 2 * spec,
         "P4_ifft_axis1": 2 * spec,
         "P5_ifft_axis2_lanczos": spec + 3 * field,        # spectrum, u_k, u_k-1 -> u_k+1
-        # u_k, d_k-1, d_k-2 -> d_k every iteration; x read and written every second one (5 fields on average)
-        "U2_direction_update": 5 * field,
+        # u_k, d_k-1, d_k-2 -> d_k every iteration; x read and written every third one (4 2/3 fields on average)
+        "U2_direction_update": 14 * field // 3,
     }
     return table.get(kind, 0) * nc
 

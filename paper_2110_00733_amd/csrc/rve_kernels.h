@@ -31,7 +31,7 @@ struct GridDims {
 // The U2 coefficients of one iteration, copied out by S2 into one of two slots (iteration parity):
 // U2 runs on a second stream beside the next iteration's operator passes, which change the state.
 struct U2Coef {
-  double cd_u, cd_d1, cd_d2, cx, cx_prev;
+  double cd_u, cd_d1, cd_d2, cx, cx_prev, cx_pp;
   int xmode;   // as MinresState::xmode
   int active;  // 0: the case had finished before this iteration; U2 does nothing
 };
@@ -45,24 +45,31 @@ struct MinresState {
   double tol_abs;                    // stop when |phibar| <= tol_abs
   double cu_v, cu_vp;                // Lanczos update coefficients (on raw u_k, u_{k-1})
   double cd_u, cd_d1, cd_d2, cx;     // search-direction / solution update coefficients
-  double cx_prev;                    // solution coefficient of the previous direction when deferred
+  double cx_prev, cx_pp;             // solution coefficients of d_{k-1}, d_{k-2} while deferred
   double sumsq;                      // scratch: last reduced sum
   int iter, max_iter, finish, done, status;
-  int xmode;    // U2's solution update: 0 defer, 1 x += cx d_k, 2 x += cx_prev d_{k-1} + cx d_k
-  int pending;  // a deferred cx_prev d_{k-1} is owed to x
+  int xmode;    // U2's solution update: 0 defer, 1 x += cx d_k, 2 x += cx_prev d_{k-1} + cx d_k,
+                // 3 x += cx_pp d_{k-2} + cx_prev d_{k-1} + cx d_k
+  int pending;  // deferred terms owed to x: 0, 1 (cx_prev d_{k-1}) or 2 (and cx_pp d_{k-2})
   int pad;
   U2Coef u2[2];  // U2's coefficients of the last two iterations (slot = iteration parity in the chunk)
 };
 
-// U2 touches x only every second iteration: the update of an even iteration is deferred and added
-// together with the next one (d_{k-1} is still in its buffer then), and a finishing iteration
-// always settles what is owed.
+// U2 touches x only every third iteration: the updates of two iterations are deferred and added
+// together with the third one's, when d_{k-1} and d_{k-2} are still in the buffers U2 reads anyway
+// (d_{k-2} is read before its buffer takes d_k); a finishing iteration always settles what is owed.
 __device__ __forceinline__ void schedule_x_update(MinresState& S) {
-  if (S.pending) {
-    S.xmode = 2;
+  if (S.pending == 2) {
+    S.xmode = 3;
     S.pending = 0;
   } else if (S.finish) {
-    S.xmode = 1;
+    S.xmode = S.pending ? 2 : 1;
+    S.pending = 0;
+  } else if (S.pending == 1) {
+    S.xmode = 0;
+    S.pending = 2;
+    S.cx_pp = S.cx_prev;
+    S.cx_prev = S.cx;
   } else {
     S.xmode = 0;
     S.pending = 1;

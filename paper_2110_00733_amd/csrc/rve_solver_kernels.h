@@ -127,7 +127,7 @@ __global__ void k_minres_init(MinresState* st, const double* partials, int np, C
     S.s1 = S.s2 = 0.0;
     S.phibar = beta;
     S.tol_abs = fmax(safety * tol * ci[cs].bnorm, inner_floor * beta);
-    S.cu_v = S.cu_vp = S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = S.cx_prev = 0.0;
+    S.cu_v = S.cu_vp = S.cd_u = S.cd_d1 = S.cd_d2 = S.cx = S.cx_prev = S.cx_pp = 0.0;
     S.xmode = 0;
     S.pending = 0;
     S.iter = 0;
@@ -188,12 +188,14 @@ __global__ void k_minres_givens(MinresState* st, const double* partials, int np,
     u.cd_d2 = S.cd_d2;
     u.cx = S.cx;
     u.cx_prev = S.cx_prev;
+    u.cx_pp = S.cx_pp;
     u.xmode = S.xmode;
     u.active = 1;
   }
 }
 
-// U2: d_k = cd_u u_k + cd_d1 d_{k-1} + cd_d2 d_{k-2} (written over d_{k-2}); x += cx d_k.
+// U2: d_k = cd_u u_k + cd_d1 d_{k-1} + cd_d2 d_{k-2} (written over d_{k-2}); the solution update
+// the slot's xmode schedules (x += cx d_k plus the terms deferred from the two previous iterations).
 // One 16-byte vector per thread over a grid that covers the field once (a grid-stride loop over a
 // fixed grid streamed about 10% slower); every load of the element is issued before its arithmetic.
 // Coefficients come from the slot S2 filled for this iteration (the live state already belongs to
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* 
   const int cs = blockIdx.y;
   const U2Coef& S = st[cs].u2[slot];
   if (!S.active) return;
-  const T a = (T)S.cd_u, b = (T)S.cd_d1, c = (T)S.cd_d2, xc = (T)S.cx, xp = (T)S.cx_prev;
+  const T a = (T)S.cd_u, b = (T)S.cd_d1, c = (T)S.cd_d2, xc = (T)S.cx, xp = (T)S.cx_prev, xpp = (T)S.cx_pp;
   const int mode = S.xmode;  // uniform per block (one case)
   const long long off = (long long)cs * n6;
   constexpr int V = VEC ? Vec16<T>::n : 1;
@@ -213,6 +215,7 @@ __global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* 
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
     if constexpr (VEC) {
       VT dv = reinterpret_cast<const VT*>(d2 + off)[i];
+      const VT d2v = dv;  // d_{k-2}, for a mode-3 solution update
       const VT uv = reinterpret_cast<const VT*>(uk + off)[i];
       const VT d1v = reinterpret_cast<const VT*>(d1 + off)[i];
       VT xv;
@@ -220,20 +223,23 @@ __global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* 
       T* de = reinterpret_cast<T*>(&dv);
       const T* ue = reinterpret_cast<const T*>(&uv);
       const T* d1e = reinterpret_cast<const T*>(&d1v);
+      const T* d2e = reinterpret_cast<const T*>(&d2v);
 #pragma unroll
       for (int e = 0; e < V; ++e) de[e] = a * ue[e] + b * d1e[e] + c * de[e];
       reinterpret_cast<VT*>(d2 + off)[i] = dv;
       if (mode != 0) {
         T* xe = reinterpret_cast<T*>(&xv);
 #pragma unroll
-        for (int e = 0; e < V; ++e) xe[e] += (mode == 2 ? xp * d1e[e] : (T)0) + xc * de[e];
+        for (int e = 0; e < V; ++e)
+          xe[e] += (mode == 3 ? xpp * d2e[e] : (T)0) + (mode >= 2 ? xp * d1e[e] : (T)0) + xc * de[e];
         reinterpret_cast<VT*>(x + off)[i] = xv;
       }
     } else {
       const T d1s = d1[off + i];
-      const T d = a * uk[off + i] + b * d1s + c * d2[off + i];
+      const T d2s = d2[off + i];
+      const T d = a * uk[off + i] + b * d1s + c * d2s;
       d2[off + i] = d;
-      if (mode != 0) x[off + i] += (mode == 2 ? xp * d1s : (T)0) + xc * d;
+      if (mode != 0) x[off + i] += (mode == 3 ? xpp * d2s : (T)0) + (mode >= 2 ? xp * d1s : (T)0) + xc * d;
     }
   }
 }
