@@ -271,6 +271,22 @@ def test_warm_start_and_iteration_cap():
     assert np.all(capped["iterations"] == 5)
 
 
+@pytest.mark.parametrize("k", [4, 5, 6])
+def test_capped_fp64_iterate_matches_oracle(k):
+    """The iterate after exactly k MINRES steps (iteration cap) equals the oracle's after k steps:
+    the solution update deferred over up to two iterations is settled whichever step the run
+    stops on (k = 4, 5, 6 stop with none, one and two deferred terms owed)."""
+    rve = _rve()
+    n = (16, 12, 20)
+    phi = li.random_phi(n, 77, 0.3)
+    E = li.uniaxial_strain(1e-3)
+    ref = oracle.solve(n, phi, C1, E, tol=1e-14, maxit=k, C0=C_SOFT, want_sigma=False)
+    out = rve.solve(_dev(phi), C1, E[None], C_void=C_SOFT, precision=rve.FP64, tol=1e-14, max_iter=k,
+                    want_stress=False)
+    assert out["status"] == rve.RVE_NOT_CONVERGED and int(out["iterations"][0]) == k
+    assert _rel(out["strain"].cpu().numpy()[0], ref["eps"]) < 1e-11
+
+
 def test_graph_replay_matches_direct_launches(monkeypatch):
     """Chunks of iterations replayed from a captured HIP graph give bit-identical results to direct
     launches (deterministic reductions), also when the cached graph is reused by a second solve."""
