@@ -50,12 +50,12 @@ def _load():
         lib.or_fft3.argtypes = [dp, ip, ctypes.c_int]
         lib.or_projection_matrix.argtypes = [ctypes.c_void_p, ip, dp, dp]
         lib.or_modified_frequency.argtypes = [ctypes.c_void_p, ip, dp, dp]
-        lib.or_apply.argtypes = [ip, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp]
-        lib.or_project.argtypes = [ip, dp, ctypes.c_int, ctypes.c_int, dp, dp]
-        lib.or_solve.argtypes = [ip, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
-                                 ctypes.c_int, dp, dp, dp, dp, dp, dp]
+        lib.or_apply.argtypes = [ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp]
+        lib.or_project.argtypes = [ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+        lib.or_solve.argtypes = [ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_double,
+                                 ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp]
         lib.or_num_threads.restype = ctypes.c_int
-        lib.or_time_minres.argtypes = [ip, dp, dp, dp, dp, ctypes.c_int]
+        lib.or_time_minres.argtypes = [ip, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int]
         lib.or_time_minres.restype = ctypes.c_double
         _lib = lib
     return _lib
@@ -63,7 +63,7 @@ def _load():
 
 class _Grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 3), ("L", ctypes.c_double * 3), ("scheme", ctypes.c_int),
-                ("nyquist", ctypes.c_int)]
+                ("nyquist", ctypes.c_int), ("stress_mask", ctypes.c_int)]
 
 
 def _dp(a):
@@ -118,13 +118,22 @@ def fft3(a: np.ndarray, sign: int = -1) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ frequencies and projection
-def _grid(n, L, scheme, nyquist):
+def _grid(n, L, scheme, nyquist, stress_mask=0):
     g = _Grid()
     g.n[:] = _n3(n)
     g.L[:] = tuple(float(v) for v in L)
     g.scheme = scheme
     g.nyquist = nyquist
+    g.stress_mask = int(stress_mask)
     return g
+
+
+def mask_of(components) -> int:
+    """Bit mask of stress-controlled Mandel components (indices 0..5 = 11, 22, 33, 23, 13, 12)."""
+    m = 0
+    for a in components:
+        m |= 1 << int(a)
+    return m
 
 
 def modified_frequency(n, m, L=(1.0, 1.0, 1.0), scheme=ROTATED) -> np.ndarray:
@@ -134,10 +143,12 @@ def modified_frequency(n, m, L=(1.0, 1.0, 1.0), scheme=ROTATED) -> np.ndarray:
     return re + 1j * im
 
 
-def projection_matrix(n, m, L=(1.0, 1.0, 1.0), scheme=ROTATED, nyquist=NYQ_NATURAL, mandel=True) -> np.ndarray:
+def projection_matrix(n, m, L=(1.0, 1.0, 1.0), scheme=ROTATED, nyquist=NYQ_NATURAL, mandel=True,
+                      stress_mask=0) -> np.ndarray:
     """Ghat at storage frequency m as a 6x6 complex matrix.  mandel=True: acting on Mandel vectors
-    (then symmetric for real Ghat); else acting on the six Cartesian components."""
-    g = _grid(n, L, scheme, nyquist)
+    (then symmetric for real Ghat); else acting on the six Cartesian components.  stress_mask: the
+    stress-controlled components (mixed control), which only change Ghat at m = 0."""
+    g = _grid(n, L, scheme, nyquist, stress_mask)
     re, im = np.zeros(36), np.zeros(36)
     _load().or_projection_matrix(ctypes.byref(g), (ctypes.c_int * 3)(*m), _dp(re), _dp(im))
     G = (re + 1j * im).reshape(6, 6)
@@ -155,7 +166,8 @@ def _fields_in(x, N):
     return np.ascontiguousarray(x)
 
 
-def apply(n, phi, C1, x, C0=None, L=(1.0, 1.0, 1.0), scheme=ROTATED, nyquist=NYQ_NATURAL) -> np.ndarray:
+def apply(n, phi, C1, x, C0=None, L=(1.0, 1.0, 1.0), scheme=ROTATED, nyquist=NYQ_NATURAL,
+          stress_mask=0) -> np.ndarray:
     """A(x) of eq. (linearOp) on a Mandel strain field x [6, *n]; returns Mandel [6, *n]."""
     n = _n3(n)
     N = int(np.prod(n))
@@ -164,33 +176,38 @@ def apply(n, phi, C1, x, C0=None, L=(1.0, 1.0, 1.0), scheme=ROTATED, nyquist=NYQ
     C0 = np.zeros(36) if C0 is None else np.ascontiguousarray(C0, dtype=np.float64).reshape(36)
     xt = _fields_in(x, N)
     y = np.empty_like(xt)
-    _load().or_apply((ctypes.c_int * 3)(*n), _dp(np.asarray(L, dtype=np.float64)), scheme, nyquist, _dp(phi),
-                     _dp(C1), _dp(C0), _dp(xt), _dp(y))
+    _load().or_apply((ctypes.c_int * 3)(*n), _dp(np.asarray(L, dtype=np.float64)), scheme, nyquist,
+                     int(stress_mask), _dp(phi), _dp(C1), _dp(C0), _dp(xt), _dp(y))
     return tensor_to_mandel(y).reshape((6,) + n)
 
 
-def project(n, x, L=(1.0, 1.0, 1.0), scheme=ROTATED, nyquist=NYQ_NATURAL) -> np.ndarray:
-    """Re F^{-1} Ghat F x on a Mandel field (projection onto compatible strain fields)."""
+def project(n, x, L=(1.0, 1.0, 1.0), scheme=ROTATED, nyquist=NYQ_NATURAL, stress_mask=0) -> np.ndarray:
+    """Re F^{-1} Ghat F x on a Mandel field (projection onto compatible strain fields; under mixed
+    control the uniform stress-controlled components are kept)."""
     n = _n3(n)
     N = int(np.prod(n))
     xt = _fields_in(x, N)
     y = np.empty_like(xt)
-    _load().or_project((ctypes.c_int * 3)(*n), _dp(np.asarray(L, dtype=np.float64)), scheme, nyquist, _dp(xt), _dp(y))
+    _load().or_project((ctypes.c_int * 3)(*n), _dp(np.asarray(L, dtype=np.float64)), scheme, nyquist,
+                       int(stress_mask), _dp(xt), _dp(y))
     return tensor_to_mandel(y).reshape((6,) + n)
 
 
 def solve(n, phi, C1, Ebar, tol=1e-8, maxit=1000, C0=None, L=(1.0, 1.0, 1.0), scheme=ROTATED,
-          nyquist=NYQ_NATURAL, solver=MINRES, x0=None, want_sigma=True) -> dict:
-    """Galerkin solve A(eps) = -A(Ebar) for the strain fluctuation (Mandel in, Mandel out).
+          nyquist=NYQ_NATURAL, solver=MINRES, x0=None, want_sigma=True, stress_mask=0, Sbar=None) -> dict:
+    """Galerkin solve of eq. (gallin) for the strain fluctuation (Mandel in, Mandel out): strain
+    control by default; with stress_mask, mixed control (those components stress-controlled at the
+    macroscopic stress Sbar, the others strain-controlled at Ebar).
 
-    Returns dict(eps [6,*n], sigma [6,*n] or None, sigma_mean [6], iterations, status,
-    rel_residual (recurrence), true_residual, bnorm, history)."""
+    Returns dict(eps [6,*n], sigma [6,*n] or None, sigma_mean [6], strain_mean [6] (total macroscopic
+    strain), iterations, status, rel_residual (recurrence), true_residual, bnorm, history)."""
     n = _n3(n)
     N = int(np.prod(n))
     phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(N)
     C1 = np.ascontiguousarray(C1, dtype=np.float64).reshape(36)
     C0 = np.zeros(36) if C0 is None else np.ascontiguousarray(C0, dtype=np.float64).reshape(36)
     E = np.ascontiguousarray(mandel_to_tensor(np.asarray(Ebar, dtype=np.float64).reshape(6)))
+    S = np.ascontiguousarray(mandel_to_tensor(np.zeros(6) if Sbar is None else np.asarray(Sbar, np.float64).reshape(6)))
     eps = np.zeros((6, N))
     sig = np.zeros((6, N)) if want_sigma else None
     smean = np.zeros(6)
@@ -200,26 +217,30 @@ def solve(n, phi, C1, Ebar, tol=1e-8, maxit=1000, C0=None, L=(1.0, 1.0, 1.0), sc
     if x0 is not None:
         x0t = _fields_in(x0, N)
         x0p = _dp(x0t)
-    _load().or_solve((ctypes.c_int * 3)(*n), _dp(np.asarray(L, dtype=np.float64)), scheme, nyquist, _dp(phi), _dp(C1),
-                     _dp(C0), _dp(E), float(tol), int(maxit), int(solver), x0p, _dp(eps),
+    _load().or_solve((ctypes.c_int * 3)(*n), _dp(np.asarray(L, dtype=np.float64)), scheme, nyquist, int(stress_mask),
+                     _dp(phi), _dp(C1), _dp(C0), _dp(E), _dp(S), float(tol), int(maxit), int(solver), x0p, _dp(eps),
                      _dp(sig) if sig is not None else None, _dp(smean), _dp(hist), _dp(info))
     it = int(info[0])
-    return dict(eps=tensor_to_mandel(eps).reshape((6,) + n),
+    Eused = np.array([0.0 if (int(stress_mask) >> a) & 1 else float(np.asarray(Ebar).reshape(6)[a]) for a in range(6)])
+    emean = tensor_to_mandel(eps).mean(axis=1)
+    return dict(eps=tensor_to_mandel(eps).reshape((6,) + n), strain_mean=Eused + emean,
                 sigma=tensor_to_mandel(sig).reshape((6,) + n) if sig is not None else None,
                 sigma_mean=tensor_to_mandel(smean), iterations=it, status=int(info[1]),
                 rel_residual=float(info[2]), true_residual=float(info[3]), bnorm=float(info[4]),
                 history=hist[:it].copy())
 
 
-def time_minres(n, phi, C1, iters=1, C0=None, L=(1.0, 1.0, 1.0)) -> float:
-    """Wall seconds of `iters` MINRES iterations (operator + vector work) on this problem."""
+def time_minres(n, phi, C1, iters=3, warmup=1, C0=None, L=(1.0, 1.0, 1.0)) -> float:
+    """Wall seconds of `iters` MINRES iterations (operator + vector work) on this problem, after all
+    vectors are allocated and first touched and `warmup` iterations have run (those are not timed).
+    The right-hand side is a seeded random field: an iteration's cost does not depend on it."""
     n = _n3(n)
     N = int(np.prod(n))
     phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(N)
     C1 = np.ascontiguousarray(C1, dtype=np.float64).reshape(36)
     C0 = np.zeros(36) if C0 is None else np.ascontiguousarray(C0, dtype=np.float64).reshape(36)
     return float(_load().or_time_minres((ctypes.c_int * 3)(*n), _dp(np.asarray(L, dtype=np.float64)), _dp(phi),
-                                        _dp(C1), _dp(C0), int(iters)))
+                                        _dp(C1), _dp(C0), int(iters), int(warmup)))
 
 
 def effective_stiffness(n, phi, C1, tol=1e-10, maxit=5000, cases=range(6), **kw) -> tuple[np.ndarray, list]:

@@ -8,11 +8,13 @@
  * What it computes (section "Galerkin-FFT with discrete differences and mixed loading control"):
  *   - voxel grid and frequencies of eq. (freq); rotated forward-difference modified frequencies of
  *     eq. (freqrot), with the product read over a dummy axis index;
- *   - the projection of eq. (galop) for pure strain control: zero at xi = 0 (all components
- *     strain-controlled), zero where the modified frequency vanishes, and
- *     [I^s_ijkl xi_j xi_l]^{-1} xi_j xi_l (symmetrised over ij and kl) elsewhere;
+ *   - the projection of eq. (galop) under mixed macroscopic control: at xi = 0 the symmetric identity
+ *     on the stress-controlled components and zero on the strain-controlled ones (pure strain control:
+ *     zero), zero where the modified frequency vanishes, and [I^s_ijkl xi_j xi_l]^{-1} xi_j xi_l
+ *     (symmetrised over ij and kl) elsewhere;
  *   - the linear operator of eq. (linearOp) with the Voigt stiffness C = phi C_solid (+ (1-phi) C_void)
- *     of section "Voigt approaches", and the right-hand side b of eq. (gallin) with sigma_bar = 0;
+ *     of section "Voigt approaches", and the right-hand side b of eq. (gallin) with the macroscopic
+ *     strain on the strain-controlled and the macroscopic stress on the stress-controlled components;
  *   - MINRES (Paige & Saunders 1975: Lanczos tridiagonalisation + Givens QR of the extended
  *     tridiagonal matrix), stopped on the residual of eq. (galres);
  *   - conjugate gradients, only to reproduce the paper's statement that CG fails with voids and
@@ -136,6 +138,8 @@ typedef struct {
   double L[3];
   int scheme;  /* 0: rotated forward differences (eq. freqrot), 1: continuous (eq. freq) */
   int nyquist; /* 0: natural (projection vanishes only where xi = 0), 1: zero at every Nyquist index */
+  int stress_mask; /* mixed macroscopic control: bit a set = component a (00,11,22,12,02,01) is
+                      stress-controlled (the set KL of eq. galop), else strain-controlled (kl) */
 } or_grid;
 
 /* signed frequency index for storage index m of an axis of length N: m for m <= (N-1)/2, else m - N;
@@ -178,7 +182,22 @@ static inline double Isym(int i, int j, int k, int l) {
   return 0.5 * ((i == k) * (j == l) + (i == l) * (j == k));
 }
 
-/* is the projection identically zero at storage frequency m? */
+static int is_zero_frequency(const int m[3]) { return m[0] == 0 && m[1] == 0 && m[2] == 0; }
+
+/* eq. (galop) at xi = 0: the symmetric identity on the stress-controlled components KL, zero on the
+ * strain-controlled ones kl (a component pair ij and its transpose ji are one component). */
+static void zero_frequency_projection(const or_grid *g, const cplx S[3][3], cplx out[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) out[i][j] = 0;
+  for (int a = 0; a < 6; ++a)
+    if (g->stress_mask & (1 << a)) {
+      int i = kI6[a], j = kJ6[a];
+      out[i][j] = S[i][j];
+      out[j][i] = S[j][i];
+    }
+}
+
+/* is the projection identically zero at storage frequency m (m != 0)? */
 static int projection_vanishes(const or_grid *g, const int m[3], const cplx xi[3]) {
   if (m[0] == 0 && m[1] == 0 && m[2] == 0) return 1; /* xi = 0, strain-controlled components */
   int nyq = 0;
@@ -233,7 +252,10 @@ void or_projection_matrix(const or_grid *g, const int m[3], double *Gre, double 
     S[kI6[b]][kJ6[b]] = 1.0;
     S[kJ6[b]][kI6[b]] = 1.0;
     cplx out[3][3] = {{0}};
-    if (!zero) apply_projection(xi, S, out);
+    if (is_zero_frequency(m))
+      zero_frequency_projection(g, S, out);
+    else if (!zero)
+      apply_projection(xi, S, out);
     for (int a = 0; a < 6; ++a) {
       Gre[a * 6 + b] = creal(out[kI6[a]][kJ6[a]]);
       Gim[a * 6 + b] = cimag(out[kI6[a]][kJ6[a]]);
@@ -301,7 +323,9 @@ static void project_work(const or_problem *P, double *y) {
     modified_frequency(&P->g, m, xi);
     cplx S[3][3], out[3][3];
     for (int a = 0; a < 6; ++a) { S[kI6[a]][kJ6[a]] = P->work[a * N + v]; S[kJ6[a]][kI6[a]] = P->work[a * N + v]; }
-    if (projection_vanishes(&P->g, m, xi)) {
+    if (is_zero_frequency(m)) {
+      zero_frequency_projection(&P->g, S, out);
+    } else if (projection_vanishes(&P->g, m, xi)) {
       memset(out, 0, sizeof(out));
     } else {
       apply_projection(xi, S, out);
@@ -332,12 +356,13 @@ static void mandel_to_tensor4(const double *Cm, double C[3][3][3][3]) {
     }
 }
 
-static void setup(or_problem *P, const int n[3], const double L[3], int scheme, int nyquist, const double *phi,
-                  const double *C1m, const double *C0m) {
+static void setup(or_problem *P, const int n[3], const double L[3], int scheme, int nyquist, int stress_mask,
+                  const double *phi, const double *C1m, const double *C0m) {
   memset(P, 0, sizeof(*P));
   for (int p = 0; p < 3; ++p) { P->g.n[p] = n[p]; P->g.L[p] = L[p]; }
   P->g.scheme = scheme;
   P->g.nyquist = nyquist;
+  P->g.stress_mask = stress_mask;
   P->phi = phi;
   P->N = (long)n[0] * n[1] * n[2];
   mandel_to_tensor4(C1m, P->C1);
@@ -348,22 +373,23 @@ static void setup(or_problem *P, const int n[3], const double L[3], int scheme, 
 static void teardown(or_problem *P) { free(P->work); }
 
 /* y = A(x), tensor components */
-void or_apply(const int n[3], const double L[3], int scheme, int nyquist, const double *phi, const double *C1m,
-              const double *C0m, const double *x, double *y) {
+void or_apply(const int n[3], const double L[3], int scheme, int nyquist, int stress_mask, const double *phi,
+              const double *C1m, const double *C0m, const double *x, double *y) {
   or_problem P;
-  setup(&P, n, L, scheme, nyquist, phi, C1m, C0m);
+  setup(&P, n, L, scheme, nyquist, stress_mask, phi, C1m, C0m);
   apply_A(&P, x, y);
   teardown(&P);
 }
 
 /* y = Re F^{-1} Ghat F x (projection onto compatible fields) */
-void or_project(const int n[3], const double L[3], int scheme, int nyquist, const double *x, double *y) {
+void or_project(const int n[3], const double L[3], int scheme, int nyquist, int stress_mask, const double *x,
+                double *y) {
   or_problem P;
   double one = 1.0, Z[36] = {0};
   long N = (long)n[0] * n[1] * n[2];
   double *phi1 = (double *)malloc(sizeof(double) * N);
   for (long v = 0; v < N; ++v) phi1[v] = one;
-  setup(&P, n, L, scheme, nyquist, phi1, Z, Z);
+  setup(&P, n, L, scheme, nyquist, stress_mask, phi1, Z, Z);
   for (long i = 0; i < 6 * N; ++i) P.work[i] = x[i];
   project_work(&P, y);
   teardown(&P);
@@ -378,27 +404,49 @@ typedef struct {
   double rel_residual;  /* recurrence estimate |phi_bar|/||b|| (MINRES) or ||r||/||b|| (CG) at exit */
   double true_residual; /* ||b - A x|| / ||b|| recomputed from x */
   double bnorm;
+  double loop_seconds;  /* wall time of the iteration loop alone (MINRES) */
 } or_result;
+
+/* MINRES vectors, each 6N doubles */
+typedef struct {
+  double *r, *v, *v_old, *p, *d1, *d2;
+} minres_vecs;
+
+static void minres_vecs_alloc(minres_vecs *w, long M) {
+  w->r = (double *)malloc(sizeof(double) * M);
+  w->v = (double *)malloc(sizeof(double) * M);
+  w->v_old = (double *)malloc(sizeof(double) * M);
+  w->p = (double *)malloc(sizeof(double) * M);
+  w->d1 = (double *)malloc(sizeof(double) * M);
+  w->d2 = (double *)malloc(sizeof(double) * M);
+}
+static void minres_vecs_free(minres_vecs *w) {
+  free(w->r); free(w->v); free(w->v_old); free(w->p); free(w->d1); free(w->d2);
+}
 
 /* MINRES for A x = b (A symmetric), x holds the start on entry and the iterate on exit.
  * Lanczos: beta_{k+1} v_{k+1} = A v_k - alpha_k v_k - beta_k v_{k-1};
- * QR of the (k+1) x k tridiagonal T_k by Givens rotations; search directions d = V R^{-1}. */
+ * QR of the (k+1) x k tridiagonal T_k by Givens rotations; search directions d = V R^{-1}.
+ * w: the vectors, or NULL to allocate them for this call. */
 static void minres_impl(const or_problem *P, const double *b, double *x, double tol, int maxit, double *hist,
-                        or_result *res, int zero_start, int final_residual);
+                        or_result *res, int zero_start, int final_residual, minres_vecs *w);
 static void minres(const or_problem *P, const double *b, double *x, double tol, int maxit, double *hist,
                    or_result *res) {
-  minres_impl(P, b, x, tol, maxit, hist, res, 0, 1);
-}
-static void minres_loop_only(const or_problem *P, const double *b, double *x, int maxit, or_result *res) {
-  minres_impl(P, b, x, 0.0, maxit, NULL, res, 1, 0);
+  minres_impl(P, b, x, tol, maxit, hist, res, 0, 1, NULL);
 }
 static void minres_impl(const or_problem *P, const double *b, double *x, double tol, int maxit, double *hist,
-                        or_result *res, int zero_start, int final_residual) {
+                        or_result *res, int zero_start, int final_residual, minres_vecs *w) {
   long M = 6 * P->N;
-  double *r = (double *)malloc(sizeof(double) * M), *v = (double *)calloc(M, sizeof(double));
-  double *v_old = (double *)calloc(M, sizeof(double)), *p = (double *)malloc(sizeof(double) * M);
-  double *d = (double *)calloc(M, sizeof(double)), *d1 = (double *)calloc(M, sizeof(double));
-  double *d2 = (double *)calloc(M, sizeof(double));
+  minres_vecs own;
+  if (!w) {
+    minres_vecs_alloc(&own, M);
+    w = &own;
+  }
+  double *r = w->r, *v = w->v, *v_old = w->v_old, *p = w->p, *d1 = w->d1, *d2 = w->d2;
+  memset(v_old, 0, sizeof(double) * M);
+  memset(d1, 0, sizeof(double) * M);
+  memset(d2, 0, sizeof(double) * M);
+  res->loop_seconds = 0.0;
   double bnorm = sqrt(frob_dot(b, b, P->N));
   res->bnorm = bnorm;
   res->status = 0;
@@ -418,6 +466,7 @@ static void minres_impl(const or_problem *P, const double *b, double *x, double 
   double phibar = beta;
   double c_km2 = 1, s_km2 = 0, c_km1 = 1, s_km1 = 0; /* rotations G_{k-2}, G_{k-1} */
   res->rel_residual = phibar / bnorm;
+  double t_loop = omp_get_wtime();
   for (int k = 1; k <= maxit; ++k) {
     /* Lanczos step */
     apply_A(P, v, p);
@@ -452,6 +501,7 @@ static void minres_impl(const or_problem *P, const double *b, double *x, double 
     for (long i = 0; i < M; ++i) { v_old[i] = v[i]; v[i] = p[i] / beta_next; }
     beta = beta_next;
   }
+  res->loop_seconds = omp_get_wtime() - t_loop;
   if (res->status == 0 && !(res->rel_residual < tol)) res->status = 1;
 done:
   res->true_residual = -1.0;
@@ -460,7 +510,7 @@ done:
     for (long i = 0; i < M; ++i) r[i] = b[i] - r[i];
     res->true_residual = (bnorm > 0) ? sqrt(frob_dot(r, r, P->N)) / bnorm : 0.0;
   }
-  free(r); free(v); free(v_old); free(p); free(d); free(d1); free(d2);
+  if (w == &own) minres_vecs_free(&own);
 }
 
 /* Conjugate gradients (Hestenes & Stiefel) on the same system, for the behavioural comparison. */
@@ -501,20 +551,36 @@ done:
 
 /* ================================================================== the homogenization solve */
 
-/* Solve A(eps) = b, b = -A(Ebar) (eq. gallin, sigma_bar = 0), for the fluctuation eps.
- * Ebar: tensor components (6).  x0: NULL for a zero start, else a start that is first projected onto
- * the compatible fields.  Outputs: eps [6][N], sigma [6][N] (may be NULL), sigma_mean [6],
- * residual history (may be NULL, length maxit).  solver: 0 MINRES, 1 CG. */
-void or_solve(const int n[3], const double L[3], int scheme, int nyquist, const double *phi, const double *C1m,
-              const double *C0m, const double *Ebar, double tol, int maxit, int solver, const double *x0,
-              double *eps, double *sigma, double *sigma_mean, double *hist, double *info) {
+/* Solve A(eps) = b, b = -F^{-1}{ Ghat : F{ C : Ebar - Sbar } } (eq. gallin), for the fluctuation eps.
+ * Mixed macroscopic control (eq. galop): components whose bit is set in stress_mask are
+ * stress-controlled, with the macroscopic stress Sbar; the others are strain-controlled, with the
+ * macroscopic strain Ebar.  Ebar's stress-controlled components and Sbar's strain-controlled ones are
+ * not used (set to zero here).  The fluctuation's mean over the stress-controlled components is the
+ * macroscopic strain they take; over the strain-controlled ones it is zero.
+ * Ebar, Sbar: tensor components (6); Sbar may be NULL (zero).  x0: NULL for a zero start, else a start
+ * that is first projected onto the admissible fields.  Outputs: eps [6][N], sigma [6][N] (may be
+ * NULL), sigma_mean [6], residual history (may be NULL, length maxit).  solver: 0 MINRES, 1 CG. */
+void or_solve(const int n[3], const double L[3], int scheme, int nyquist, int stress_mask, const double *phi,
+              const double *C1m, const double *C0m, const double *Ebar, const double *Sbar, double tol, int maxit,
+              int solver, const double *x0, double *eps, double *sigma, double *sigma_mean, double *hist,
+              double *info) {
   or_problem P;
-  setup(&P, n, L, scheme, nyquist, phi, C1m, C0m);
+  setup(&P, n, L, scheme, nyquist, stress_mask, phi, C1m, C0m);
   long N = P.N, M = 6 * N;
   double *b = (double *)malloc(sizeof(double) * M), *E = (double *)malloc(sizeof(double) * M);
+  double Es[6], Ss[6];
+  for (int a = 0; a < 6; ++a) {
+    int kl = !(stress_mask & (1 << a));
+    Es[a] = kl ? Ebar[a] : 0.0;
+    Ss[a] = (!kl && Sbar) ? Sbar[a] : 0.0;
+  }
   for (int a = 0; a < 6; ++a)
-    for (long v = 0; v < N; ++v) E[a * N + v] = Ebar[a];
-  apply_A(&P, E, b);
+    for (long v = 0; v < N; ++v) E[a * N + v] = Es[a];
+  /* the field C : Ebar - Sbar, transformed and projected */
+  stiffness(&P, E, NULL, P.work);
+  for (int a = 0; a < 6; ++a)
+    for (long v = 0; v < N; ++v) P.work[a * N + v] -= Ss[a];
+  project_work(&P, b);
   for (long i = 0; i < M; ++i) b[i] = -b[i];
   if (x0) {
     for (long i = 0; i < M; ++i) P.work[i] = x0[i];
@@ -545,27 +611,40 @@ void or_solve(const int n[3], const double L[3], int scheme, int nyquist, const 
   teardown(&P);
 }
 
-/* Timing sample for the CPU baseline: `iters` MINRES iterations of A x = v on the given problem, with
- * v a seeded pseudo-random tensor field (a zero start needs no operator application before the
- * loop).  Returns wall seconds spent in the iterations only. */
+/* Timing sample for the CPU baseline: MINRES iterations of A x = b on the given problem, b a seeded
+ * pseudo-random tensor field (the cost of an iteration does not depend on b), zero start.  Every
+ * vector is allocated and first touched, and `warmup` iterations run, before the timed run of `iters`
+ * iterations; only its iteration loop is timed.  Returns those wall seconds. */
 double or_time_minres(const int n[3], const double L[3], const double *phi, const double *C1m, const double *C0m,
-                      int iters) {
+                      int iters, int warmup) {
   or_problem P;
-  setup(&P, n, L, 0, 0, phi, C1m, C0m);
+  setup(&P, n, L, 0, 0, 0, phi, C1m, C0m);
   long M = 6 * P.N;
-  double *b = (double *)malloc(sizeof(double) * M), *x = (double *)calloc(M, sizeof(double));
+  double *b = (double *)malloc(sizeof(double) * M), *x = (double *)malloc(sizeof(double) * M);
   uint64_t st = 0x9E3779B97F4A7C15ULL;
   for (long i = 0; i < M; ++i) {
     st ^= st << 13; st ^= st >> 7; st ^= st << 17; /* xorshift64 */
     b[i] = (double)(st >> 11) * 0x1.0p-53 - 0.5;
   }
+  minres_vecs w;
+  minres_vecs_alloc(&w, M);
+  /* first touch of every buffer the loop uses, with the threads that later use them */
+  double *bufs[7] = {w.r, w.v, w.v_old, w.p, w.d1, w.d2, x};
+  for (int k = 0; k < 7; ++k) {
+    double *a = bufs[k];
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < M; ++i) a[i] = 0.0;
+  }
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < M; ++i) P.work[i] = 0.0;
   or_result res;
-  double t0 = omp_get_wtime();
-  minres_loop_only(&P, b, x, iters, &res);
-  double t1 = omp_get_wtime();
+  if (warmup > 0) minres_impl(&P, b, x, 0.0, warmup, NULL, &res, 1, 0, &w);
+  memset(x, 0, sizeof(double) * M);
+  minres_impl(&P, b, x, 0.0, iters, NULL, &res, 1, 0, &w);
+  minres_vecs_free(&w);
   free(b); free(x);
   teardown(&P);
-  return t1 - t0;
+  return res.loop_seconds;
 }
 
 int or_num_threads(void) {

@@ -112,3 +112,33 @@ def laminate_closed_form(profile, axis: int, E: float, nu: float) -> np.ndarray:
     S[inplane[0], inplane[1]] = S[inplane[1], inplane[0]] = nu * Ep
     S[shear, shear] = 2 * mu
     return H * Cm + (A - H) * S
+
+
+def mixed_solution(n, phi, C1, Ebar, stress_components, Sbar, C0=None, L=(1.0, 1.0, 1.0)):
+    """Mixed macroscopic control by dense minimisation: the strain is Ebar (strain-controlled
+    components only) + m + eps, with eps a compatible zero-mean stencil strain and m a uniform strain
+    in the stress-controlled components; (eps, m) minimise the energy 1/2 <(E + m + eps) C (E + m + eps)>
+    minus the work <Sbar . m> of the prescribed macroscopic stress.  Minimum-norm least squares where
+    empty voxels make it singular.
+
+    Returns (fluctuation eps + m [6,*n], sigma [6,*n], sigma_mean [6], strain_mean [6])."""
+    n = tuple(int(v) for v in n)
+    N = n[0] * n[1] * n[2]
+    KL = sorted(int(a) for a in stress_components)
+    Q = compatible_basis(n, L)
+    M = np.zeros((6 * N, len(KL)))
+    for j, a in enumerate(KL):
+        M[a * N:(a + 1) * N, j] = 1.0
+    Z = np.concatenate([Q, M], axis=1)
+    C = stiffness_matrix(phi, C1, C0)
+    Eb = np.array([0.0 if a in KL else float(Ebar[a]) for a in range(6)])
+    E = np.repeat(Eb.reshape(6, 1), N, axis=1).reshape(-1)
+    Sb = np.array([float(Sbar[a]) if a in KL else 0.0 for a in range(6)])
+    s = np.repeat(Sb.reshape(6, 1), N, axis=1).reshape(-1)  # the uniform prescribed stress field
+    Kz = Z.T @ C @ Z
+    rhs = -Z.T @ (C @ E) + Z.T @ s
+    y = np.linalg.lstsq(Kz, rhs, rcond=1e-12)[0]
+    fl = Z @ y
+    sig = C @ (E + fl)
+    return (fl.reshape((6,) + n), sig.reshape((6,) + n), sig.reshape(6, N).mean(axis=1),
+            Eb + fl.reshape(6, N).mean(axis=1))

@@ -136,6 +136,149 @@ def test_minres_matches_dense_min_norm_solution(n, seed):
     assert np.abs(r["eps"] - e).max() < 1e-9 * np.abs(e).max()
 
 
+def _random_spd_mandel(seed, scale):
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((6, 6))
+    return scale * (a @ a.T / 6 + np.eye(6))
+
+
+@pytest.mark.parametrize("n,seed", [((4, 4, 4), 15), ((4, 6, 8), 16), ((5, 3, 4), 17)])
+def test_operator_with_soft_phase_matches_dense(n, seed):
+    """A(x) = Ghat : C(x) : x with C(x) = phi C1 + (1 - phi) C0 (section "Voigt approaches") for an
+    anisotropic soft phase C0: against the dense projector onto the stencil strains (SVD, no FFT) applied
+    to the dense block stiffness."""
+    L = (1.0, 0.8, 1.2)
+    phi = li.random_phi(n, seed, 0.4).astype(np.float64)
+    C0 = _random_spd_mandel(seed, 0.05)
+    Cs = _random_spd_mandel(seed + 100, 1.0)
+    Q = bf.compatible_basis(n, L)
+    K = bf.stiffness_matrix(phi, Cs, C0)
+    x = li.random_field((6,) + n, seed + 1)
+    ref = Q @ (Q.T @ (K @ x.reshape(-1)))
+    got = oracle.apply(n, phi, Cs, x, C0=C0, L=L).reshape(-1)
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    # the soft-phase term is really there: dropping it changes the result at first order
+    no_c0 = oracle.apply(n, phi, Cs, x, L=L).reshape(-1)
+    assert np.abs(no_c0 - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,seed", [((4, 4, 4), 25), ((4, 6, 8), 26), ((5, 3, 4), 27)])
+def test_minres_with_soft_phase_matches_dense_solution(n, seed):
+    """With a soft instead of an empty phase the energy is positive definite on the compatible fields,
+    so the solution is unique: the oracle's MINRES solve against the dense solve, strain, stress and
+    average stress (all six components, anisotropic phases)."""
+    L = (1.0, 0.8, 1.2)
+    phi = li.random_phi(n, seed, 0.4).astype(np.float64)
+    C0 = _random_spd_mandel(seed, 0.05)
+    Cs = _random_spd_mandel(seed + 100, 1.0)
+    E = np.array([0.4, -0.2, 0.1, 0.3, -0.15, 0.05])
+    e, s, sm = bf.min_norm_solution(n, phi, Cs, E, C0=C0, L=L)
+    r = oracle.solve(n, phi, Cs, E, tol=1e-13, maxit=3000, C0=C0, L=L)
+    assert r["status"] == 0 and r["true_residual"] < 1e-11
+    assert np.abs(r["sigma_mean"] - sm).max() < 1e-12 * np.abs(sm).max()
+    assert np.abs(r["sigma"] - s).max() < 1e-11 * np.abs(s).max()
+    assert np.abs(r["eps"] - e).max() < 1e-10 * np.abs(e).max()
+
+
+@pytest.mark.parametrize("n,axis,prof,c", [((8, 4, 4), 0, [1, 1, 1, 1, .25, .25, .25, .25], 0.1),
+                                           ((5, 6, 3), 1, [1, 0.5, 0, 0.75, 1, 1], 0.02),
+                                           ((4, 4, 8), 2, [0.3, 1, 0, 0.8, 1, 0.6, 0.1, 0.9], 0.3)])
+def test_laminate_with_soft_phase_closed_form(n, axis, prof, c):
+    """Soft phase C0 = c C1: the Voigt stiffness is (phi + (1 - phi) c) C1, a laminate of the solid
+    with the layer profile psi = phi + (1 - phi) c, whose closed form (Voigt in-plane, Reuss across)
+    fixes C_eff; a void layer becomes a layer of stiffness c C1."""
+    phi = li.laminate_phi(n, axis, prof)
+    Ce, _ = oracle.effective_stiffness(n, phi, C1, tol=1e-13, maxit=500, C0=c * C1)
+    psi = np.asarray(prof, dtype=np.float32).astype(np.float64)
+    psi = psi + (1.0 - psi) * c
+    ref = bf.laminate_closed_form(psi, axis, 1.0, 0.3)
+    assert np.abs(Ce - ref).max() < 1e-11
+
+
+# ------------------------------------------------------------------ mixed macroscopic control
+def test_zero_frequency_projection_mixed_control():
+    """eq. (galop) at xi = 0: the identity on the stress-controlled components, zero on the others."""
+    for comps in ([], [1, 2, 3, 4, 5], [0, 3], [5]):
+        mask = oracle.mask_of(comps)
+        G = oracle.projection_matrix((6, 4, 5), (0, 0, 0), stress_mask=mask)
+        assert np.array_equal(G, np.diag([1.0 if a in comps else 0.0 for a in range(6)]).astype(complex))
+        # every other frequency is unchanged by the mask
+        assert np.array_equal(oracle.projection_matrix((6, 4, 5), (1, 2, 3), stress_mask=mask),
+                              oracle.projection_matrix((6, 4, 5), (1, 2, 3)))
+
+
+@pytest.mark.parametrize("n,seed,comps,soft", [((4, 4, 4), 31, [1, 2, 3, 4, 5], True),
+                                               ((4, 6, 8), 32, [0, 3], True),
+                                               ((5, 3, 4), 33, [2, 4, 5], False),
+                                               ((4, 4, 4), 34, [1, 2, 3, 4, 5], False)])
+def test_mixed_control_matches_dense_minimisation(n, seed, comps, soft):
+    """Mixed control (eq. galop at xi = 0, eq. gallin with the macroscopic stress) against the dense
+    minimisation of the energy minus the work of the prescribed stress over compatible fluctuations and
+    uniform stress-controlled strains; with a soft phase (unique) and with empty voxels (min-norm)."""
+    L = (1.0, 0.8, 1.2)
+    phi = li.random_phi(n, seed, 0.5 if soft else 0.3).astype(np.float64)
+    C0 = 0.05 * C1 if soft else None
+    E = np.array([0.4, -0.2, 0.1, 0.3, -0.15, 0.05])
+    S = np.array([0.02, -0.01, 0.03, 0.015, -0.02, 0.01])
+    mask = oracle.mask_of(comps)
+    fl, sig, sm, em = bf.mixed_solution(n, phi, C1, E, comps, S, C0=C0, L=L)
+    r = oracle.solve(n, phi, C1, E, tol=1e-13, maxit=4000, C0=C0, L=L, stress_mask=mask, Sbar=S)
+    assert r["status"] == 0 and r["true_residual"] < 1e-11
+    assert np.abs(r["sigma_mean"] - sm).max() < 1e-11 * np.abs(sm).max()
+    assert np.abs(r["sigma_mean"][comps] - S[comps]).max() < 1e-11 * np.abs(sm).max()
+    assert np.abs(r["strain_mean"] - em).max() < 1e-10 * np.abs(em).max()
+    assert np.abs(r["sigma"] - sig).max() < 1e-10 * np.abs(sig).max()
+    assert np.abs(r["eps"] - fl).max() < 1e-9 * np.abs(fl).max()
+
+
+def test_mixed_control_consistent_with_effective_stiffness():
+    """The macroscopic state of a mixed solve satisfies <sigma> = C_eff <eps> with C_eff from six
+    strain-controlled solves; uniaxial stress gives E = 1/S_00 and nu = -S_10/S_00, S = C_eff^-1 (the
+    uniaxial-stress modulus and Poisson ratio the paper reports)."""
+    n = (6, 5, 4)
+    phi = li.random_phi(n, 35, 0.5).astype(np.float64)
+    C0 = 0.02 * C1
+    Ce, _ = oracle.effective_stiffness(n, phi, C1, tol=1e-13, maxit=4000, C0=C0)
+    Sc = np.linalg.inv(Ce)
+    r = oracle.solve(n, phi, C1, li.uniaxial_strain(1.0), tol=1e-13, maxit=4000, C0=C0,
+                     stress_mask=oracle.mask_of([1, 2, 3, 4, 5]))
+    assert r["status"] == 0
+    E_mod = r["sigma_mean"][0] / r["strain_mean"][0]
+    nu = -r["strain_mean"][1] / r["strain_mean"][0]
+    assert abs(E_mod - 1.0 / Sc[0, 0]) < 1e-10 * E_mod
+    assert abs(nu + Sc[1, 0] / Sc[0, 0]) < 1e-9
+    # a general mixed state: two strain-controlled, four stress-controlled components
+    comps = [1, 2, 4, 5]
+    E = np.array([1e-3, 0, 0, 4e-4, 0, 0])
+    S = np.array([0, 2e-5, -1e-5, 0, 3e-6, -2e-6])
+    r = oracle.solve(n, phi, C1, E, tol=1e-13, maxit=4000, C0=C0, stress_mask=oracle.mask_of(comps), Sbar=S)
+    assert np.abs(r["sigma_mean"] - Ce @ r["strain_mean"]).max() < 1e-10 * np.abs(r["sigma_mean"]).max()
+    assert np.abs(r["sigma_mean"][comps] - S[comps]).max() < 1e-12
+    assert np.abs(r["strain_mean"][[0, 3]] - E[[0, 3]]).max() < 1e-15
+
+
+@pytest.mark.parametrize("n,axis,prof", [((8, 4, 4), 0, [1, 1, 1, 1, .25, .25, .25, .25]),
+                                         ((4, 6, 4), 1, [0.3, 1, 0.2, 0.8, 1, 0.6]),
+                                         ((4, 4, 5), 2, [0.5, 1, 0.15, 0.9, 0.7])])
+@pytest.mark.parametrize("load_axis", [0, 1, 2])
+def test_laminate_uniaxial_stress_closed_form(n, axis, prof, load_axis):
+    """Uniaxial stress on a laminate along and across its layers: E = 1 / (C_lam^-1)_pp and
+    nu = -(C_lam^-1)_qp / (C_lam^-1)_pp from the laminate closed form (Voigt in-plane, Reuss across)."""
+    phi = li.laminate_phi(n, axis, prof)
+    ref = bf.laminate_closed_form(np.asarray(prof, dtype=np.float32), axis, 1.0, 0.3)
+    Sc = np.linalg.inv(ref)
+    comps = [a for a in range(6) if a != load_axis]
+    E = np.zeros(6)
+    E[load_axis] = 1e-3
+    r = oracle.solve(n, phi, C1, E, tol=1e-13, maxit=500, stress_mask=oracle.mask_of(comps))
+    assert r["status"] == 0
+    E_mod = r["sigma_mean"][load_axis] / r["strain_mean"][load_axis]
+    assert abs(E_mod - 1.0 / Sc[load_axis, load_axis]) < 1e-10
+    q = (load_axis + 1) % 3
+    nu = -r["strain_mean"][q] / r["strain_mean"][load_axis]
+    assert abs(nu + Sc[q, load_axis] / Sc[load_axis, load_axis]) < 1e-9
+
+
 def _laminate_cases():
     rng = np.random.default_rng(11)
     prof_rand = rng.uniform(0.1, 1.0, 8)
