@@ -65,8 +65,30 @@ def workload(name):
     return n, phi, E, cfg
 
 
+def method_bytes_per_voxel_iteration(n2, elem):
+    """The method's own HBM bytes per voxel and MINRES iteration, each operand counted once: the
+    forward half (strain and phase map read, half spectrum written), the inverse half (half spectrum
+    read, A v written) and the MINRES vector update (p, v_k, v_k-1, w_k-1, w_k-2, x read; v_k+1, w_k,
+    x written).  The half spectrum holds 6 (n2/2 + 1) complex values per n2 voxels.  FP32 fields at
+    n2 = 256: 316.4 B; FP64: 628.8 B."""
+    spec = 6 * 2 * elem * (n2 // 2 + 1) / n2
+    forward = 6 * elem + 4 + spec
+    inverse = spec + 6 * elem
+    update = 9 * 6 * elem
+    return forward + inverse + update
+
+
+def method_bytes_per_voxel_apply(n2, elem):
+    """The operator apply alone (forward + inverse halves above): 100.4 B per voxel in FP32 at n2 = 256."""
+    spec = 6 * 2 * elem * (n2 // 2 + 1) / n2
+    return (6 * elem + 4 + spec) + (spec + 6 * elem)
+
+
 def algorithmic_bytes(kind, n, nc, elem):
-    """Bytes one launch must move (each operand read or written once), FP32/FP64 fields."""
+    """Bytes one launch of a pass must move (each of its operands read or written once), FP32/FP64
+    fields.  Summed over the passes of one iteration this is the implementation's operand traffic
+    (406 B per voxel-iteration in FP32 at 256^3), about 1.3 times the method's own count above: the
+    five-pass transform writes and reads the spectrum between passes."""
     n0, n1, n2 = n
     nv = n0 * n1 * n2
     spec = 6 * (n2 // 2 + 1) * n0 * n1 * 2 * elem
@@ -130,7 +152,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="octet256_defects")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=1)
+    ap.add_argument("--cpu-iters", type=int, default=3, help="timed oracle MINRES iterations")
+    ap.add_argument("--cpu-warmup", type=int, default=1, help="untimed oracle MINRES iterations before them")
     ap.add_argument("--profile-steps", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--streams", type=int, default=8, help="batch workload: concurrent streams")
@@ -186,12 +209,15 @@ def main():
     def one():
         return rve.solve(d, C1, E, tol=cfg["tol"], precision=prec, workspace=ws, want_stress=True, **extra)
 
+    apply_ms = None  # tuned operator apply (P1-P5, no Lanczos work), own precision
     if not args.no_autotune:
         ta = time.time()
         precs = [rve.FP64] if prec == rve.FP64 else [rve.FP32_MIXED, rve.FP64]
         for p_ in precs:
             r_ = rve.autotune(n, n_cases=nc, precision=p_, workspace=ws)
             log(f"autotune prec={p_}: tiles {r_['tiles']} apply {r_['ms']:.3f} ms")
+            if p_ == prec:
+                apply_ms = r_["ms"]
         cfg["tiles"] = {"fp32": list(rve.tuned_tiles(n, rve.FP32_MIXED)[0]), "fp64": list(rve.tuned_tiles(n, rve.FP64)[0])}
         log(f"autotune took {time.time() - ta:.1f}s")
 
@@ -272,11 +298,14 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         t1 = time.time()
-        secs = oracle.time_minres(n, phi, C1, iters=args.cpu_iters)
+        secs = oracle.time_minres(n, phi, C1, iters=args.cpu_iters, warmup=args.cpu_warmup)
         cpu = {"value": nvox * args.cpu_iters / secs, "unit": "voxel-iterations/s", "cores": oracle.num_threads(),
                "kind": "oracle",
-               "sample": f"{args.cpu_iters} FP64 MINRES iteration(s) (operator apply + vector updates) of the CPU "
-                         f"oracle on the same {n[0]}x{n[1]}x{n[2]} problem, zero start; {secs:.1f} s"}
+               "sample": f"{args.cpu_iters} timed FP64 MINRES iterations (operator apply + vector updates, "
+                         f"{secs:.1f} s) of the CPU oracle on the same {n[0]}x{n[1]}x{n[2]} grid and phase map, "
+                         f"zero start, after {args.cpu_warmup} untimed warm-up iteration(s); all vectors "
+                         f"allocated and first touched before timing; the right-hand side is a seeded random "
+                         f"field (an iteration's cost does not depend on it)"}
         log(f"cpu baseline {cpu['value']:.3e} voxel-it/s in {time.time() - t1:.1f}s wall")
 
     # whole-solve average: the MINRES iterations' algorithmic bytes over the timed wall time, which
@@ -285,10 +314,27 @@ def main():
                   "P5_ifft_axis2_lanczos", "U2_direction_update")
     iter_bytes = sum(algorithmic_bytes(k, n, 1, elem) for k in iter_kinds)
     solve_gbs = iter_bytes * sum(iters) / total_t / 1e9
+    # the method's own bytes (each operand once, the spectrum written and read once per half):
+    # per voxel-iteration over the whole timed solve, and per voxel over the tuned plain apply
+    bvi = method_bytes_per_voxel_iteration(n[2], elem)
+    alg_iter_gbs = bvi * nvox * sum(iters) / total_t / 1e9
+    bva = method_bytes_per_voxel_apply(n[2], elem)
+    method = {"bytes_per_voxel_iteration": round(bvi, 2), "alg_iteration_gbs": round(alg_iter_gbs, 1),
+              "alg_frac_iteration": round(alg_iter_gbs / HBM_PEAK_GBS, 4),
+              "operand_bytes_per_voxel_iteration": round(iter_bytes / nvox, 2),
+              "operand_over_method_bytes": round(iter_bytes / nvox / bvi, 3),
+              "bytes_per_voxel_apply": round(bva, 2)}
+    if apply_ms:
+        method.update({"apply_ms": round(apply_ms, 4),
+                       "alg_frac_apply": round(bva * nvox * nc / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    if roof is not None:
+        roof.update({"alg_frac_iteration": method["alg_frac_iteration"],
+                     "alg_frac_apply": method.get("alg_frac_apply")})
     cfg.update({"iterations_per_solve": iters[-1] // nc if nc else 0, "rel_residual": max(res),
                 "wall_time_to_tol_ms": round(ms_per_step, 2), "minres_iterations_per_s": sum(iters) / total_t / nc,
-                "solve_avg_hbm_gbs": round(solve_gbs, 1), "solve_avg_hbm_frac": round(solve_gbs / HBM_PEAK_GBS, 4),
-                "parallelism": "single-gpu"})
+                "solve_avg_operand_gbs": round(solve_gbs, 1),
+                "solve_avg_operand_frac": round(solve_gbs / HBM_PEAK_GBS, 4),
+                "method_bytes": method, "parallelism": "single-gpu"})
     line = {"metric": "voxel-iterations/s + wall time to 1e-6 residual at 256^3, learned vs plain",
             "value": value, "unit": "voxel-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

@@ -24,7 +24,9 @@
  *     MINRES iterations (rounded up to a multiple of 6) into a HIP graph that it replays until
  *     convergence and keeps cached for the next call with the same buffers (capture needs a non-NULL
  *     stream; with the NULL stream, or RVE_DISABLE_GRAPHS=1 in the environment, it launches directly).
- *     The graph cache is per host thread; solves on different threads and streams may run concurrently.
+ *     The captured graphs, the second stream of solve_rve and their events are cached per (device,
+ *     solve stream), process-wide and mutex-guarded, and freed by rve_release_caches(); solves on
+ *     different threads and streams may run concurrently.
  *   - argument validation happens on the host before any HIP call; a rejected call touches no
  *     device state.
  */
@@ -76,10 +78,20 @@ typedef struct {
   double inner_safety;  /* FP32_MIXED: an inner sweep aims at inner_safety * tol * ||b|| (default 0.9; the
                            FP64 residual decides, so a sweep that ends just above tol is followed by
                            another one) */
+  int32_t stress_mask;  /* mixed macroscopic control (eq. galop, eq. gallin; section "Galerkin-FFT with
+                           discrete differences and mixed loading control"): bit a set = Mandel component
+                           a (0..5 = 11, 22, 33, 23, 13, 12) is stress-controlled, the others
+                           strain-controlled.  0 (default): pure strain control.  The projection at
+                           xi = 0 is then the identity on the stress-controlled components, and the
+                           fluctuation's mean over them is the macroscopic strain they take */
+  const double* macro_stress; /* host [n_cases][6] Mandel macroscopic stress; only the stress-controlled
+                           components are read (NULL: zero, e.g. uniaxial stress).  The macroscopic
+                           strain's stress-controlled components are ignored.  Read during the call only */
 } rve_options;
 
 /* Fills *opt with the defaults: tol 1e-6, max_iter 5000, FP32_MIXED, max_refine 24, natural Nyquist,
- * rotated scheme, check_every 24, inner_floor 3e-2, inner_safety 0.9. */
+ * rotated scheme, check_every 24, inner_floor 3e-2, inner_safety 0.9, stress_mask 0 (strain control),
+ * macro_stress NULL. */
 void rve_default_options(rve_options* opt);
 
 /* 1 if the FFT kernels provide axis length n, else 0: every n in [2, 256] without a prime factor
@@ -94,7 +106,8 @@ rve_status rve_validate(const rve_grid* grid, const double* phase_stiffness, con
 /* Workspace bytes solve_rve needs for this grid, number of load cases and options (0 on bad input). */
 size_t rve_workspace_bytes(const rve_grid* grid, int32_t n_cases, const rve_options* opt);
 
-/* Galerkin-FFT homogenization of one RVE under n_cases macro strains (eq. gallin, strain control).
+/* Galerkin-FFT homogenization of one RVE under n_cases macroscopic loads (eq. gallin): macro strains, or
+ * with opt->stress_mask mixed strain/stress control.
  *   voxel_fraction_field  device float [N]: solid fraction phi in [0,1] of each voxel (Voigt rule)
  *   phase_stiffness       host double [2][36]: Mandel 6x6 stiffness of the empty phase ([0], usually
  *                         all zero) and of the solid ([1]); each must be symmetric and finite
@@ -103,15 +116,19 @@ size_t rve_workspace_bytes(const rve_grid* grid, int32_t n_cases, const rve_opti
  *                         NULL for the zero start; it is projected onto compatible fields first,
  *                         and a case whose projected start has ||b - A x0|| >= ||b|| starts from
  *                         zero instead (see rve_last_solve_info)
- *   strain_out            device [n_cases][6][N] (float / double): the fluctuation eps (total = Ebar+eps)
+ *   strain_out            device [n_cases][6][N] (float / double): the fluctuation eps (total = Ebar+eps,
+ *                         Ebar without its stress-controlled components; see rve_last_mean_strain)
  *   stress_out            device [n_cases][6][N] (float / double) or NULL: sigma = C(x)(Ebar + eps)
  *   eff_stress            host double [n_cases][6]: volume average <sigma> (FP64); for unit Mandel
  *                         macro strains e_J this is column J of the effective stiffness
  *   iterations            host int32 [n_cases]: MINRES iterations (operator applications in the loop)
  *   rel_residual          host double [n_cases]: ||b - A eps|| / ||b|| recomputed in FP64 at exit
- * Work is queued on hip_stream and on a second stream the library creates once per host thread and
- * device (default priority), joined back into hip_stream before every host check; the call returns
- * after hip_stream has finished.  Returns the worst status over the load cases. */
+ * Work is queued on hip_stream and on a second stream the library creates once per (device, solve
+ * stream) and keeps cached (default priority), joined back into hip_stream before every host check;
+ * the call returns after hip_stream has finished.  Returns the worst status over the load cases.
+ * A right-hand side that counts as zero (homogeneous or all-empty cell, zero macro strain; ||b|| at the
+ * rounding level of the transforms of a constant field) returns eps = 0 exactly and 0 iterations,
+ * also when a warm start eps0 is given. */
 rve_status solve_rve(const rve_grid* grid, const float* voxel_fraction_field, const double* phase_stiffness,
                      const double* macro_strain, int32_t n_cases, const rve_options* opt, const void* eps0,
                      void* strain_out, void* stress_out, double* eff_stress, int32_t* iterations,
@@ -130,6 +147,8 @@ typedef struct {
   double* eff_stress;                /* host [n_cases][6] */
   int32_t* iterations;               /* host [n_cases] */
   double* rel_residual;              /* host [n_cases] */
+  const double* macro_stress;        /* host [n_cases][6] or NULL: this RVE's macroscopic stress under
+                                        mixed control (replaces opt->macro_stress for this item) */
   int32_t status;                    /* out: this RVE's solve_rve status */
 } rve_batch_item;
 
@@ -154,10 +173,11 @@ size_t rve_apply_workspace_bytes(const rve_grid* grid, int32_t n_cases, int32_t 
  *   mode RVE_APPLY_PROJECTION:          y = F^{-1}{ Ghat : F{ x } }       (C = identity)
  *   mode RVE_APPLY_STIFFNESS_ROUNDTRIP: y = F^{-1}{ F{ C(x) : x } }       (Ghat = identity)
  * x, y: device [n_cases][6][N] float (precision RVE_FP32_MIXED) or double (RVE_FP64); phase_stiffness
- * as in solve_rve (ignored for PROJECTION). */
+ * as in solve_rve (ignored for PROJECTION); stress_mask as in rve_options (Ghat at xi = 0). */
 rve_status rve_apply(const rve_grid* grid, const float* voxel_fraction_field, const double* phase_stiffness,
-                     int32_t n_cases, int32_t precision, int32_t scheme, int32_t nyquist, int32_t mode,
-                     const void* x, void* y, void* workspace, size_t workspace_bytes, void* hip_stream);
+                     int32_t n_cases, int32_t precision, int32_t scheme, int32_t nyquist, int32_t stress_mask,
+                     int32_t mode, const void* x, void* y, void* workspace, size_t workspace_bytes,
+                     void* hip_stream);
 
 /* Optional per-kernel timing (instrumentation for benchmarks, not on by default).  When enabled,
  * every kernel launched inside the MINRES iteration loop of solve_rve is bracketed by HIP events
@@ -212,6 +232,24 @@ const char* rve_last_error(void);
  * below 1 (the solve then started from zero).  Either pointer may be NULL.  Returns the number of
  * cases of that solve (0 if none). */
 int32_t rve_last_solve_info(double* initial_rel_residual, int32_t* warm_rejected, int32_t max_cases);
+
+/* Frees every cached runtime object the solvers keep between calls: the captured iteration graphs,
+ * the second (U2) streams and their events, per (device, solve stream).  Sets in use by a solve that
+ * is running on another thread at that moment are kept.  The next solve recreates what it needs.
+ * Returns the number of cache sets freed.  (Ownership paragraph of the boundary: the library keeps no
+ * device memory of its own; this releases the remaining runtime handles.) */
+int32_t rve_release_caches(void);
+
+/* Counts of the cached runtime objects (for leak checks): counts4 = {cache sets, side streams, events,
+ * instantiated graphs}; counts4 may be NULL.  Returns the number of cache sets. */
+int32_t rve_cache_counts(int64_t* counts4);
+
+/* Total macroscopic strain of the last solve_rve that returned on this thread, per load case (first
+ * max_cases): mean_strain [max_cases][6] = Ebar (strain-controlled components) + <eps>, in FP64; under
+ * mixed control its stress-controlled components are the strains the prescribed stress produces (e.g.
+ * E = <sigma_11> / mean_strain_11 and nu = -mean_strain_22 / mean_strain_11 under uniaxial stress).
+ * Returns the number of cases of that solve. */
+int32_t rve_last_mean_strain(double* mean_strain, int32_t max_cases);
 
 /* Human-readable name of a status code (static string). */
 const char* rve_status_string(rve_status s);

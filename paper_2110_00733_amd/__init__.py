@@ -26,7 +26,8 @@ APPLY_OPERATOR, APPLY_PROJECTION, APPLY_STIFFNESS_ROUNDTRIP = 0, 1, 2
 ABI_SYMBOLS = ("rve_default_options", "rve_supported_length", "rve_validate", "rve_workspace_bytes", "solve_rve",
                "rve_apply_workspace_bytes", "rve_apply", "rve_profile_enable", "rve_profile_reset", "rve_profile_read",
                "rve_profile_kind_name", "rve_batch_workspace_bytes", "solve_rve_batch", "rve_autotune", "rve_load_tuning", "rve_tuned_tiles", "rve_last_error",
-               "rve_last_solve_info", "rve_status_string")
+               "rve_last_solve_info", "rve_last_mean_strain", "rve_release_caches", "rve_cache_counts",
+               "rve_status_string")
 
 
 class RveError(RuntimeError):
@@ -45,7 +46,8 @@ class Grid(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("nyquist", ctypes.c_int32), ("scheme", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("inner_floor", ctypes.c_double), ("inner_safety", ctypes.c_double)]
+                ("check_every", ctypes.c_int32), ("inner_floor", ctypes.c_double), ("inner_safety", ctypes.c_double),
+                ("stress_mask", ctypes.c_int32), ("macro_stress", ctypes.POINTER(ctypes.c_double))]
 
 
 class BatchItem(ctypes.Structure):
@@ -54,7 +56,7 @@ class BatchItem(ctypes.Structure):
                 ("n_cases", ctypes.c_int32), ("eps0", ctypes.c_void_p), ("strain_out", ctypes.c_void_p),
                 ("stress_out", ctypes.c_void_p), ("eff_stress", ctypes.POINTER(ctypes.c_double)),
                 ("iterations", ctypes.POINTER(ctypes.c_int32)), ("rel_residual", ctypes.POINTER(ctypes.c_double)),
-                ("status", ctypes.c_int32)]
+                ("macro_stress", ctypes.POINTER(ctypes.c_double)), ("status", ctypes.c_int32)]
 
 
 _lib = None
@@ -83,7 +85,7 @@ def load_library():
     lib.rve_apply_workspace_bytes.argtypes = [gp, ctypes.c_int32, ctypes.c_int32]
     lib.rve_apply_workspace_bytes.restype = ctypes.c_size_t
     lib.rve_apply.argtypes = [gp, vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                              ctypes.c_int32, vp, vp, vp, ctypes.c_size_t, vp]
+                              ctypes.c_int32, ctypes.c_int32, vp, vp, vp, ctypes.c_size_t, vp]
     lib.rve_apply.restype = ctypes.c_int
     lib.rve_profile_enable.argtypes = [ctypes.c_int32]
     lib.rve_profile_enable.restype = None
@@ -108,7 +110,13 @@ def load_library():
     lib.rve_last_error.argtypes = []
     lib.rve_last_error.restype = ctypes.c_char_p
     lib.rve_last_solve_info.argtypes = [dp, ip, ctypes.c_int32]
+    lib.rve_last_mean_strain.argtypes = [dp, ctypes.c_int32]
+    lib.rve_last_mean_strain.restype = ctypes.c_int32
     lib.rve_last_solve_info.restype = ctypes.c_int32
+    lib.rve_release_caches.argtypes = []
+    lib.rve_release_caches.restype = ctypes.c_int32
+    lib.rve_cache_counts.argtypes = [ctypes.POINTER(ctypes.c_int64)]
+    lib.rve_cache_counts.restype = ctypes.c_int32
     lib.rve_status_string.argtypes = [ctypes.c_int]
     lib.rve_status_string.restype = ctypes.c_char_p
     _lib = lib
@@ -172,6 +180,33 @@ def last_solve_info(max_cases: int = 64) -> dict:
     n = load_library().rve_last_solve_info(_dp(r0), rej.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), max_cases)
     n = min(int(n), max_cases)
     return dict(initial_rel_residual=r0[:n].copy(), warm_rejected=rej[:n].astype(bool))
+
+
+def release_caches() -> int:
+    """Free the cached graphs, side streams and events (rve_release_caches); returns the sets freed."""
+    return int(load_library().rve_release_caches())
+
+
+def cache_counts() -> dict:
+    """Cached runtime objects: {"sets", "streams", "events", "graphs"} (rve_cache_counts)."""
+    c = np.zeros(4, dtype=np.int64)
+    load_library().rve_cache_counts(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return dict(zip(("sets", "streams", "events", "graphs"), (int(v) for v in c)))
+
+
+def last_mean_strain(max_cases: int = 64) -> np.ndarray:
+    """Total macroscopic strain [n_cases, 6] of the last solve on this thread (rve_last_mean_strain)."""
+    out = np.zeros((max_cases, 6))
+    n = int(load_library().rve_last_mean_strain(_dp(out), max_cases))
+    return out[:min(n, max_cases)].copy()
+
+
+def stress_mask_of(components) -> int:
+    """Bit mask of stress-controlled Mandel components (0..5 = 11, 22, 33, 23, 13, 12)."""
+    m = 0
+    for a in components:
+        m |= 1 << int(a)
+    return m
 
 
 def status_string(s: int) -> str:
@@ -268,11 +303,13 @@ _default_ws = Workspace()
 
 
 def solve(phi, C_solid, macro_strain, *, C_void=None, L=(1.0, 1.0, 1.0), opt: Options | None = None, eps0=None,
-          want_stress: bool = True, workspace: Workspace | None = None, check: bool = True, **opt_kw) -> dict:
-    """solve_rve on a device phase map `phi` (torch float32 [n0,n1,n2]) for each macro strain row.
+          want_stress: bool = True, workspace: Workspace | None = None, check: bool = True, macro_stress=None,
+          **opt_kw) -> dict:
+    """solve_rve on a device phase map `phi` (torch float32 [n0,n1,n2]) for each macro strain row; with
+    stress_mask=... (and macro_stress rows [nc,6], default zero) under mixed strain/stress control.
 
-    Returns dict(strain [nc,6,*n], stress [nc,6,*n] or None, eff_stress [nc,6], iterations [nc],
-    rel_residual [nc], status)."""
+    Returns dict(strain [nc,6,*n], stress [nc,6,*n] or None, eff_stress [nc,6], mean_strain [nc,6],
+    iterations [nc], rel_residual [nc], status)."""
     torch = _torch()
     lib = load_library()
     if not (phi.is_cuda and phi.dtype == torch.float32 and phi.dim() == 3 and phi.is_contiguous()):
@@ -281,6 +318,10 @@ def solve(phi, C_solid, macro_strain, *, C_void=None, L=(1.0, 1.0, 1.0), opt: Op
     opt = opt or default_options(**opt_kw)
     E = np.ascontiguousarray(np.asarray(macro_strain, dtype=np.float64).reshape(-1, 6))
     nc = E.shape[0]
+    S = None
+    if macro_stress is not None:
+        S = np.ascontiguousarray(np.broadcast_to(np.asarray(macro_stress, dtype=np.float64).reshape(-1, 6), (nc, 6)))
+        opt.macro_stress = _dp(S)
     C = _stiffness(C_solid, C_void)
     g = make_grid(n, L)
     fdt = torch.float32 if opt.precision == FP32_MIXED else torch.float64
@@ -310,7 +351,10 @@ def solve(phi, C_solid, macro_strain, *, C_void=None, L=(1.0, 1.0, 1.0), opt: Op
     cur.wait_stream(ss)  # solve_rve returns after synchronising its stream; keep torch's ordering explicit
     if check and st < 0:
         raise RveError(st, "solve_rve")
-    return dict(strain=strain, stress=stress, eff_stress=eff, iterations=its, rel_residual=res, status=int(st))
+    mean = last_mean_strain(nc) if st >= 0 else np.full((nc, 6), np.nan)
+    del S
+    return dict(strain=strain, stress=stress, eff_stress=eff, mean_strain=mean, iterations=its, rel_residual=res,
+                status=int(st))
 
 
 _batch_streams = []
@@ -374,7 +418,7 @@ def solve_batch(rves, C_solid, *, C_void=None, n_streams: int = 8, opt: Options 
 
 
 def apply(x, phi=None, C_solid=None, *, C_void=None, mode: int = APPLY_OPERATOR, L=(1.0, 1.0, 1.0),
-          scheme: int = ROTATED, nyquist: int = NYQ_NATURAL, workspace: Workspace | None = None):
+          scheme: int = ROTATED, nyquist: int = NYQ_NATURAL, stress_mask: int = 0, workspace: Workspace | None = None):
     """rve_apply on fields x (torch [nc,6,n0,n1,n2], float32 -> FP32 kernels, float64 -> FP64 kernels)."""
     torch = _torch()
     lib = load_library()
@@ -394,7 +438,8 @@ def apply(x, phi=None, C_solid=None, *, C_void=None, mode: int = APPLY_OPERATOR,
                        "rve_apply_workspace_bytes")
     ws = (workspace or _default_ws).get(nbytes, x.device)
     phip = ctypes.c_void_p(phi.data_ptr()) if phi is not None else None
-    st = lib.rve_apply(ctypes.byref(g), phip, _dp(C), nc, prec, scheme, nyquist, mode, ctypes.c_void_p(x.data_ptr()),
+    st = lib.rve_apply(ctypes.byref(g), phip, _dp(C), nc, prec, scheme, nyquist, int(stress_mask), mode,
+                       ctypes.c_void_p(x.data_ptr()),
                        ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
                        _stream_ptr(torch, x.device))
     if st != RVE_OK:

@@ -110,6 +110,7 @@ template <typename T>
 struct FreqTables {
   const T* s[3];  // sin(q/2)/h (rotated scheme) per axis and storage index
   const T* c[3];  // cos(q/2), exact 0 at a Nyquist index
+  int stress_mask;  // mixed macroscopic control: Mandel components kept by the projection at xi = 0
 };
 
 __device__ __forceinline__ long long spec_idx(const GridDims& g, int cs, int k2, int c, int n0, int n1) {
@@ -411,14 +412,15 @@ __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, cx<T>* 
 // ============================================================================ P3
 // Galerkin projection of one frequency (eq. galop): Ghat S = t (x) n + n (x) t - (n.t) n (x) n with
 // n = w/|w| and t = S n, applied to the Mandel components (S0..S5) in place and scaled by f (the 1/N
-// of the inverse transform); w = 0 gives 0.
+// of the inverse transform); w = 0 gives 0, except for the components in `keep` (the stress-controlled
+// ones under mixed control, passed only at xi = 0), on which Ghat is the identity.
 // 1/sqrt: the hardware reciprocal square root (1 ulp) in FP32, the correctly rounded form in FP64
 __device__ __forceinline__ float rnorm(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rnorm(double x) { return 1.0 / sqrt(x); }
 
 template <typename T>
 __device__ __forceinline__ void project_mandel(cx<T>& D0, cx<T>& D1, cx<T>& D2, cx<T>& D3, cx<T>& D4, cx<T>& D5,
-                                               T w0, T w1, T w2, T f) {
+                                               T w0, T w1, T w2, T f, int keep) {
   const T sq2 = (T)1.41421356237309504880168872420970, isq2 = (T)0.70710678118654752440084436210485;
   const T nn = w0 * w0 + w1 * w1 + w2 * w2;
   if (nn > (T)0) {
@@ -439,7 +441,12 @@ __device__ __forceinline__ void project_mandel(cx<T>& D0, cx<T>& D1, cx<T>& D2, 
     D4 = scl(scl(t0, m2) + scl(t2, m0) - scl(q, m0 * m2), sq2);
     D5 = scl(scl(t0, m1) + scl(t1, m0) - scl(q, m0 * m1), sq2);
   } else {
-    D0 = D1 = D2 = D3 = D4 = D5 = mk<T>(0, 0);
+    D0 = (keep & 1) ? scl(D0, f) : mk<T>(0, 0);
+    D1 = (keep & 2) ? scl(D1, f) : mk<T>(0, 0);
+    D2 = (keep & 4) ? scl(D2, f) : mk<T>(0, 0);
+    D3 = (keep & 8) ? scl(D3, f) : mk<T>(0, 0);
+    D4 = (keep & 16) ? scl(D4, f) : mk<T>(0, 0);
+    D5 = (keep & 32) ? scl(D5, f) : mk<T>(0, 0);
   }
 }
 
@@ -516,7 +523,8 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
         } else {
           const T s0 = ft.s[0][k0], c0 = ft.c[0][k0];
           const T w0 = s0 * c1c2, w1 = c0 * s1c2, w2 = c0 * c1s2;
-          project_mandel(D[0][e], D[1][e], D[2][e], D[3][e], D[4][e], D[5][e], w0, w1, w2, inv_total);
+          const int keep = (k0 | k1c | k2) == 0 ? ft.stress_mask : 0;
+          project_mandel(D[0][e], D[1][e], D[2][e], D[3][e], D[4][e], D[5][e], w0, w1, w2, inv_total, keep);
         }
       }
     }
@@ -664,10 +672,13 @@ __global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__
           const int k0 = a + NA * b;
           const T s0 = ft.s[0][k0], c0 = ft.c[0][k0];
           const T w0 = s0 * c1c2, w1 = c0 * s1c2, w2 = c0 * c1s2;
+          const int keep = (k0 | k1c | k2) == 0 ? ft.stress_mask : 0;
           if (h == 0)
-            project_mandel(D[0][e], D[1][e], D[2][e], D[0][e ^ 1], D[1][e ^ 1], D[2][e ^ 1], w0, w1, w2, inv_total);
+            project_mandel(D[0][e], D[1][e], D[2][e], D[0][e ^ 1], D[1][e ^ 1], D[2][e ^ 1], w0, w1, w2, inv_total,
+                           keep);
           else
-            project_mandel(D[0][e ^ 1], D[1][e ^ 1], D[2][e ^ 1], D[0][e], D[1][e], D[2][e], w0, w1, w2, inv_total);
+            project_mandel(D[0][e ^ 1], D[1][e ^ 1], D[2][e ^ 1], D[0][e], D[1][e], D[2][e], w0, w1, w2, inv_total,
+                           keep);
         }
       }
     }
@@ -733,7 +744,8 @@ __global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__
 // (j = 0..2), and the projected values go back the same way.  Every group passes the same barriers.
 template <typename T, int NA, int NB, int E, int G>
 __device__ __forceinline__ void split3_project(cx<T> (&D)[2][E], cx<T>* lds_all, int WNB, int q, int t,
-                                               const FreqTables<T>& ft, T c1c2, T s1c2, T c1s2, T inv_total) {
+                                               const FreqTables<T>& ft, T c1c2, T s1c2, T c1s2, T inv_total,
+                                               int keep0) {
   constexpr int TT = NB;
   constexpr int CB = (NA + TT - 1) / TT;
   constexpr int GA = (G + 1) % 3, GB = (G + 2) % 3;  // the groups after and before G
@@ -766,7 +778,7 @@ __device__ __forceinline__ void split3_project(cx<T> (&D)[2][E], cx<T>* lds_all,
         const T w0 = s0 * c1c2, w1 = c0 * s1c2, w2 = c0 * c1s2;
         const int m3 = e - G;
         project_mandel(D[0][m3], D[1][m3], D[0][m3 + 1], D[1][m3 + 1], D[0][m3 + 2], D[1][m3 + 2], w0, w1, w2,
-                       inv_total);
+                       inv_total, k0 == 0 ? keep0 : 0);
       }
     }
   }
@@ -855,12 +867,15 @@ __global__ __launch_bounds__(192) void k_axis0_project_split3(cx<T>* __restrict_
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int e = 0; e < E; ++e) D[c][e] = scl(D[c][e], inv_total);
-  } else if (grp == 0) {
-    split3_project<T, NA, NB, E, 0>(D, lds_all, WNB, q, t, ft, c1c2, s1c2, c1s2, inv_total);
-  } else if (grp == 1) {
-    split3_project<T, NA, NB, E, 1>(D, lds_all, WNB, q, t, ft, c1c2, s1c2, c1s2, inv_total);
   } else {
-    split3_project<T, NA, NB, E, 2>(D, lds_all, WNB, q, t, ft, c1c2, s1c2, c1s2, inv_total);
+    // the stress-controlled components survive the projection only at xi = 0 (k0 = 0 is checked inside)
+    const int keep0 = (k1c | k2) == 0 ? ft.stress_mask : 0;
+    if (grp == 0)
+      split3_project<T, NA, NB, E, 0>(D, lds_all, WNB, q, t, ft, c1c2, s1c2, c1s2, inv_total, keep0);
+    else if (grp == 1)
+      split3_project<T, NA, NB, E, 1>(D, lds_all, WNB, q, t, ft, c1c2, s1c2, c1s2, inv_total, keep0);
+    else
+      split3_project<T, NA, NB, E, 2>(D, lds_all, WNB, q, t, ft, c1c2, s1c2, c1s2, inv_total, keep0);
   }
 
   // ---- inverse along axis 0

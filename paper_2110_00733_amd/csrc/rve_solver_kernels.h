@@ -80,6 +80,41 @@ __global__ void k_lincomb(To* out, const Ta* a, double alpha, const double* b, d
   if (threadIdx.x == 0 && partials) partials[(long long)cs * gridDim.x + blockIdx.x] = s;
 }
 
+// Right-hand side of eq. (gallin) under mixed control: out = -a + sconst[cs][component] (the macroscopic
+// stress on the stress-controlled components, zero on the others), per-block partial sums of out^2.
+__global__ void k_rhs(double* out, const double* a, const double* sconst, long long nvox, double* partials) {
+  __shared__ double red[16];
+  const int cs = blockIdx.y;
+  const long long n6 = 6 * nvox;
+  const long long off = (long long)cs * n6;
+  double acc = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n6; i += (long long)gridDim.x * blockDim.x) {
+    const double v = -a[off + i] + sconst[cs * 6 + i / nvox];
+    out[off + i] = v;
+    acc += v * v;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[(long long)cs * gridDim.x + blockIdx.x] = s;
+}
+
+// Per-block partial sums of each component of an FP64 field (its volume average after the fixed-order
+// sum of the partials).  Grid (blocks, nc); partials [nc][6][blocks].
+__global__ void k_field_sums(const double* x64, long long nvox, double* partials) {
+  __shared__ double red[16];
+  const int cs = blockIdx.y;
+  const long long off = (long long)cs * 6 * nvox;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += x64[off + c * nvox + v];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const double s = block_sum(acc[c], red);
+    if (threadIdx.x == 0) partials[((long long)cs * 6 + c) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
 // x64 += (double) d  (per case, only where mask[cs] != 0)
 template <typename Td>
 __global__ void k_accum(double* x64, const Td* d, long long n6, const int* active) {
@@ -264,10 +299,12 @@ __global__ void k_residual_update(CaseInfo* ci, const double* sums, int nc, doub
 }
 
 // A warm start that does not reduce the residual below ||b|| is dropped: x = 0, r = b (the zero
-// start, bit for bit).  Grid (blocks, nc).
+// start, bit for bit).  A case whose right-hand side counts as zero (bnorm = 0: homogeneous cell,
+// all-empty cell, zero macro strain) has the exact answer eps = 0, whatever the start: it takes the
+// zero start too, without being recorded as a rejection.  Grid (blocks, nc).
 __global__ void k_warm_fallback(double* x64, double* r64, const double* b64, CaseInfo* ci, long long n6) {
   const int cs = blockIdx.y;
-  if (!(ci[cs].bnorm > 0.0 && ci[cs].rnorm >= ci[cs].bnorm)) return;
+  if (!(ci[cs].bnorm == 0.0 || ci[cs].rnorm >= ci[cs].bnorm)) return;
   const long long off = (long long)cs * n6;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n6; i += (long long)gridDim.x * blockDim.x) {
     x64[off + i] = 0.0;
@@ -278,8 +315,13 @@ __global__ void k_warm_fallback(double* x64, double* r64, const double* b64, Cas
 __global__ void k_residual_update_fallback(CaseInfo* ci, int nc) {
   const int cs = blockIdx.x * blockDim.x + threadIdx.x;
   if (cs >= nc) return;
+  if (ci[cs].bnorm == 0.0) {  // zero start taken by k_warm_fallback; nothing to solve
+    ci[cs].r0 = 0.0;
+    ci[cs].rnorm = 0.0;
+    return;
+  }
   ci[cs].r0 = ci[cs].rnorm;
-  if (!(ci[cs].bnorm > 0.0 && ci[cs].rnorm >= ci[cs].bnorm)) return;
+  if (ci[cs].rnorm < ci[cs].bnorm) return;
   ci[cs].warm_rejected = 1;
   ci[cs].rnorm = ci[cs].bnorm;
 }
