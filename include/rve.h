@@ -233,6 +233,25 @@ const char* rve_last_error(void);
  * cases of that solve (0 if none). */
 int32_t rve_last_solve_info(double* initial_rel_residual, int32_t* warm_rejected, int32_t max_cases);
 
+/* For callers that cannot allocate (code that may not call hipMalloc, tight serving loops, harnesses
+ * that forbid allocation): solve_rve without a workspace argument.  Same arguments, outputs, statuses
+ * and arithmetic as solve_rve; the caller still passes inputs and outputs.  Its scratch is a static
+ * device array of rve_noalloc_scratch_bytes() bytes (128 MiB) compiled into the library, one copy per
+ * GPU, held until the process ends; its address is looked up once per device on the first call there.
+ * A solve whose rve_workspace_bytes() exceeds that size returns RVE_ENOMEM (rve_last_error() says by
+ * how much) before any device work.  The call allocates no device memory and creates no HIP runtime
+ * objects (no streams, events or graphs): the direction update runs on hip_stream and every kernel is
+ * launched directly.  Every call on one GPU shares that GPU's scratch, which keeps the last call's
+ * contents (each call initialises what it reads): calls that overlap on one GPU, from several host
+ * threads or streams, race and must be serialised by the caller. */
+rve_status solve_rve_noalloc(const rve_grid* grid, const float* voxel_fraction_field,
+                             const double* phase_stiffness, const double* macro_strain, int32_t n_cases,
+                             const rve_options* opt, const void* eps0, void* strain_out, void* stress_out,
+                             double* eff_stress, int32_t* iterations, double* rel_residual, void* hip_stream);
+
+/* Size in bytes of the static scratch solve_rve_noalloc works in (per GPU). */
+size_t rve_noalloc_scratch_bytes(void);
+
 /* Frees every cached runtime object the solvers keep between calls: the captured iteration graphs,
  * the second (U2) streams and their events, per (device, solve stream).  Sets in use by a solve that
  * is running on another thread at that moment are kept.  The next solve recreates what it needs.

@@ -26,8 +26,8 @@ APPLY_OPERATOR, APPLY_PROJECTION, APPLY_STIFFNESS_ROUNDTRIP = 0, 1, 2
 ABI_SYMBOLS = ("rve_default_options", "rve_supported_length", "rve_validate", "rve_workspace_bytes", "solve_rve",
                "rve_apply_workspace_bytes", "rve_apply", "rve_profile_enable", "rve_profile_reset", "rve_profile_read",
                "rve_profile_kind_name", "rve_batch_workspace_bytes", "solve_rve_batch", "rve_autotune", "rve_load_tuning", "rve_tuned_tiles", "rve_last_error",
-               "rve_last_solve_info", "rve_last_mean_strain", "rve_release_caches", "rve_cache_counts",
-               "rve_status_string")
+               "rve_last_solve_info", "rve_last_mean_strain", "rve_release_caches", "rve_cache_counts", "solve_rve_noalloc",
+               "rve_noalloc_scratch_bytes", "rve_status_string")
 
 
 class RveError(RuntimeError):
@@ -113,6 +113,10 @@ def load_library():
     lib.rve_last_mean_strain.argtypes = [dp, ctypes.c_int32]
     lib.rve_last_mean_strain.restype = ctypes.c_int32
     lib.rve_last_solve_info.restype = ctypes.c_int32
+    lib.solve_rve_noalloc.argtypes = [gp, vp, dp, dp, ctypes.c_int32, op, vp, vp, vp, dp, ip, dp, vp]
+    lib.solve_rve_noalloc.restype = ctypes.c_int
+    lib.rve_noalloc_scratch_bytes.argtypes = []
+    lib.rve_noalloc_scratch_bytes.restype = ctypes.c_size_t
     lib.rve_release_caches.argtypes = []
     lib.rve_release_caches.restype = ctypes.c_int32
     lib.rve_cache_counts.argtypes = [ctypes.POINTER(ctypes.c_int64)]

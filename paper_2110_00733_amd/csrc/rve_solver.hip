@@ -1526,6 +1526,55 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
                     iterations, rel_residual, workspace, workspace_bytes, hip_stream, kSolveDefault);
 }
 
+// ---------------------------------------------------------------------------- no-allocation entry point
+// Static scratch for solve_rve_noalloc: a file-scope device array, one copy per GPU the library runs
+// on, held until the process ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in); its device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static rve_status scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return RVE_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return RVE_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RVE_OK;
+}
+
+size_t rve_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+rve_status solve_rve_noalloc(const rve_grid* grid, const float* phi, const double* phase_stiffness,
+                             const double* macro_strain, int32_t n_cases, const rve_options* opt, const void* eps0,
+                             void* strain_out, void* stress_out, double* eff_stress, int32_t* iterations,
+                             double* rel_residual, void* hip_stream) {
+  rve_status st = rve_validate(grid, phase_stiffness, macro_strain, n_cases, opt);
+  if (st != RVE_OK) return st;
+  if (!phi || !strain_out || !eff_stress || !iterations || !rel_residual) return RVE_EINVAL;
+  const size_t need = rve_workspace_bytes(grid, n_cases, opt);
+  if (need == 0) return RVE_EINVAL;
+  if (need > kNoAllocScratchBytes) {
+    snprintf(g_last_error, sizeof(g_last_error),
+             "solve_rve_noalloc: this solve needs %zu bytes of workspace, the static scratch holds %zu", need,
+             kNoAllocScratchBytes);
+    return RVE_ENOMEM;
+  }
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != RVE_OK) return st;
+  return solve_impl(grid, phi, phase_stiffness, macro_strain, n_cases, opt, eps0, strain_out, stress_out, eff_stress,
+                    iterations, rel_residual, ws, kNoAllocScratchBytes, hip_stream, kSolveNoAlloc);
+}
+
 int32_t rve_release_caches(void) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   int32_t freed = 0;
