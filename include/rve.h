@@ -55,6 +55,7 @@ enum { RVE_FP32_MIXED = 0, RVE_FP64 = 1 };
 enum { RVE_SCHEME_ROTATED = 0, RVE_SCHEME_CONTINUOUS = 1 };
 enum { RVE_NYQ_NATURAL = 0, RVE_NYQ_ZERO_ALL = 1 };
 enum { RVE_APPLY_OPERATOR = 0, RVE_APPLY_PROJECTION = 1, RVE_APPLY_STIFFNESS_ROUNDTRIP = 2 };
+enum { RVE_ALPHA_CV = 0, RVE_ALPHA_AV = 1 };
 
 typedef struct {
   int32_t n[3]; /* voxels per axis, each a length rve_supported_length() accepts */
@@ -87,11 +88,16 @@ typedef struct {
   const double* macro_stress; /* host [n_cases][6] Mandel macroscopic stress; only the stress-controlled
                            components are read (NULL: zero, e.g. uniaxial stress).  The macroscopic
                            strain's stress-controlled components are ignored.  Read during the call only */
+  int32_t alpha_mode;   /* Lanczos diagonal alpha_k of MINRES: RVE_ALPHA_CV (default) = <v_k, C v_k>, formed
+                           in the stiffness pass, equal to <v_k, A v_k> for a compatible v_k because Ghat
+                           is an orthogonal projector; RVE_ALPHA_AV = <v_k, A v_k> from the last inverse
+                           pass, which then stores A v_k and a separate pass applies the three-term
+                           Lanczos update (one more field pass per iteration, no compatibility assumed) */
 } rve_options;
 
 /* Fills *opt with the defaults: tol 1e-6, max_iter 5000, FP32_MIXED, max_refine 24, natural Nyquist,
  * rotated scheme, check_every 24, inner_floor 3e-2, inner_safety 0.9, stress_mask 0 (strain control),
- * macro_stress NULL. */
+ * macro_stress NULL, alpha_mode RVE_ALPHA_CV. */
 void rve_default_options(rve_options* opt);
 
 /* 1 if the FFT kernels provide axis length n, else 0: every n in [2, 256] without a prime factor

@@ -21,6 +21,7 @@ FP32_MIXED, FP64 = 0, 1
 ROTATED, CONTINUOUS = 0, 1
 NYQ_NATURAL, NYQ_ZERO_ALL = 0, 1
 APPLY_OPERATOR, APPLY_PROJECTION, APPLY_STIFFNESS_ROUNDTRIP = 0, 1, 2
+ALPHA_CV, ALPHA_AV = 0, 1
 
 # every symbol include/rve.h declares
 ABI_SYMBOLS = ("rve_default_options", "rve_supported_length", "rve_validate", "rve_workspace_bytes", "solve_rve",
@@ -47,7 +48,8 @@ class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("nyquist", ctypes.c_int32), ("scheme", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("inner_floor", ctypes.c_double), ("inner_safety", ctypes.c_double),
-                ("stress_mask", ctypes.c_int32), ("macro_stress", ctypes.POINTER(ctypes.c_double))]
+                ("stress_mask", ctypes.c_int32), ("macro_stress", ctypes.POINTER(ctypes.c_double)),
+                ("alpha_mode", ctypes.c_int32)]
 
 
 class BatchItem(ctypes.Structure):

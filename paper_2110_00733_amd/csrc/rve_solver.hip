@@ -444,7 +444,7 @@ template <typename T>
 static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, const float* phi,
                      const Material<T>& mat, const Tables<T>& tb, cx<T>* spec, T* y, const T* uk, const T* ukm1,
                      double* partials, MinresState* st, int identity, hipStream_t s, int u2_slot = 0,
-                     hipEvent_t before_p5 = nullptr, hipEvent_t after_p2 = nullptr) {
+                     hipEvent_t before_p5 = nullptr, hipEvent_t after_p2 = nullptr, int alpha_av = 0) {
   constexpr int el = (int)sizeof(T);
   const LenKernels<T>& K0 = axis(pl, el, 0)->k<T>();
   const LenKernels<T>& K1 = axis(pl, el, 1)->k<T>();
@@ -468,9 +468,9 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     dim3 grid((g.n1 + W - 1) / W, g.n0, nc);
     prof::begin<T>(prof::P1, s);
     hipLaunchKernelGGL(K2.p1, grid, dim3(W * nb2), lds, s, x, xscale, (int)(sizeof(MinresState) / sizeof(double)),
-                       phi, mat, spec, tb.tw[2], g, W, st, uk ? partials : nullptr);
+                       phi, mat, spec, tb.tw[2], g, W, st, (uk && !alpha_av) ? partials : nullptr);
     prof::end(s);
-    if (uk) {
+    if (uk && !alpha_av) {
       prof::begin<T>(prof::S1, s);
       hipLaunchKernelGGL(k_minres_alpha, dim3(nc), dim3(256), 0, s, st, partials, (int)(grid.x * grid.y));
     }
@@ -525,12 +525,24 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     // P5 overwrites the field an earlier iteration's U2 (second stream) may still be reading
     if (before_p5) (void)hipStreamWaitEvent(s, before_p5, 0);
     prof::begin<T>(prof::P5, s);
-    hipLaunchKernelGGL(K2.p5, grid, dim3(W * nb2), lds, s, spec, y, uk, ukm1, partials, tb.tw[2], g, W, st);
+    hipLaunchKernelGGL(K2.p5, grid, dim3(W * nb2), lds, s, spec, y, uk, ukm1, partials, tb.tw[2], g, W, st,
+                       alpha_av);
     prof::end(s);
+    int np2 = (int)(grid.x * grid.y);
+    if (uk && alpha_av) {
+      // alpha = <v_k, A v_k> from P5's partials, then the three-term update on the stored A v_k
+      prof::begin<T>(prof::S1, s);
+      hipLaunchKernelGGL(k_minres_alpha, dim3(nc), dim3(256), 0, s, st, partials, np2);
+      prof::end(s);
+      prof::begin<T>(prof::P5, s);  // timed as part of the inverse-transform + Lanczos step
+      hipLaunchKernelGGL(k_lanczos<T>, dim3(kRedBlocks, nc), dim3(kThreads), 0, s, y, uk, ukm1, st, 6 * g.nvox,
+                         partials);
+      prof::end(s);
+      np2 = kRedBlocks;
+    }
     if (uk) {
       prof::begin<T>(prof::S2, s);
-      hipLaunchKernelGGL(k_minres_givens, dim3(nc), dim3(256), 0, s, st, partials, (int)(grid.x * grid.y),
-                         u2_slot);
+      hipLaunchKernelGGL(k_minres_givens, dim3(nc), dim3(256), 0, s, st, partials, np2, u2_slot);
     }
     prof::end(s);
   }
@@ -633,6 +645,7 @@ struct LoopCtx {
   StreamCache* cache = nullptr;  // nullptr: U2 inline on the solve stream, no graph
   bool u2_inline = false;        // batch workers and profiled solves keep U2 on the solve stream
   bool allow_graph = true;
+  int alpha_av = 0;              // alpha = <v, A v> after P5 instead of <v, C v> in P1 (RVE_ALPHA_AV)
 };
 
 static rve_status u2_events(U2Side& U, int count, bool need_stream) {
@@ -653,7 +666,7 @@ static rve_status u2_events(U2Side& U, int count, bool need_stream) {
 template <typename T>
 static rve_status enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, const float* phi,
                                      const Material<T>& mat, const Tables<T>& tb, cx<T>* spec, MinresState* st,
-                                     double* part, int count, int ph[5], hipStream_t s, U2Side* U) {
+                                     double* part, int count, int ph[5], hipStream_t s, U2Side* U, int alpha_av) {
   const long long n6 = 6 * pl.g.nvox;
   dim3 vg, vb;
   vec_grid(nc, &vg, &vb);
@@ -676,7 +689,8 @@ static rve_status enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, c
   };
   if (!U) {
     for (int j = 0; j < count; ++j) {
-      apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s, j & 1);
+      apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s, j & 1,
+                  nullptr, nullptr, alpha_av);
       launch_u2(s, j, id2, id1, ib);
       const int t0 = ia;
       ia = ib;
@@ -699,7 +713,7 @@ static rve_status enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, c
     // iteration j's operator; U2(j-1) starts when P2(j) is done and streams beside P3(j), the pass
     // that leaves the most bandwidth unused
     apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s, j & 1,
-                j >= 2 ? U->after_u2[j - 2] : nullptr, j >= 1 ? U->after_p2[j] : nullptr);
+                j >= 2 ? U->after_u2[j - 2] : nullptr, j >= 1 ? U->after_p2[j] : nullptr, alpha_av);
     if (j >= 1) {
       const rve_status r2 = u2(j - 1, prev[0], prev[1], prev[2], U->after_p2[j]);
       if (r2 != RVE_OK) return r2;
@@ -725,7 +739,8 @@ static rve_status enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, c
 template <typename T>
 static std::vector<unsigned char> chunk_key(const Plan& pl, int nc, const MinresBufs<T>& B, const float* phi,
                                             const Material<T>& mat, const Tables<T>& tb, const cx<T>* spec,
-                                            const MinresState* st, const double* part, int chunk, bool inl) {
+                                            const MinresState* st, const double* part, int chunk, bool inl,
+                                            int alpha_av) {
   std::vector<unsigned char> k;
   auto put = [&](const void* p, size_t n) {
     const unsigned char* c = static_cast<const unsigned char*>(p);
@@ -744,6 +759,7 @@ static std::vector<unsigned char> chunk_key(const Plan& pl, int nc, const Minres
   put(&part, sizeof(part));
   put(&chunk, sizeof(chunk));
   put(&inl, sizeof(inl));  // the captured graph has U2 on a side stream or inline
+  put(&alpha_av, sizeof(alpha_av));
   return k;
 }
 
@@ -774,13 +790,14 @@ static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const fl
   bool use_graph = ctx.cache && ctx.allow_graph && graphs_enabled() && !prof::on && s != nullptr;
   ChunkGraph* G = use_graph ? &ctx.cache->graph[sizeof(T) == 8 ? 1 : 0] : nullptr;
   if (use_graph) {
-    std::vector<unsigned char> key = chunk_key<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk, inl);
+    std::vector<unsigned char> key = chunk_key<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk, inl, ctx.alpha_av);
     if (G->exec == nullptr || G->key != key) {
       G->reset();
       int ph[5] = {0, 1, 2, 0, 1};
       bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
-        const rve_status er = enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk, ph, s, U);
+        const rve_status er =
+            enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk, ph, s, U, ctx.alpha_av);
         const hipError_t le = hipGetLastError();
         hipGraph_t gr = nullptr;
         ok = hipStreamEndCapture(s, &gr) == hipSuccess && le == hipSuccess && gr != nullptr && er == RVE_OK;
@@ -808,7 +825,7 @@ static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const fl
       it += chunk;
     } else {
       const int n = std::min(check, max_iter - it);
-      const rve_status er = enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, n, ph, s, U);
+      const rve_status er = enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, n, ph, s, U, ctx.alpha_av);
       if (er != RVE_OK) return er;
       it += n;
     }
@@ -847,6 +864,7 @@ void rve_default_options(rve_options* o) {
   o->inner_safety = 0.9;
   o->stress_mask = 0;
   o->macro_stress = nullptr;
+  o->alpha_mode = RVE_ALPHA_CV;
 }
 
 int32_t rve_supported_length(int32_t n) {
@@ -1167,6 +1185,7 @@ static rve_status validate_options(const rve_options* o) {
   if (!(o->inner_floor > 0 && o->inner_floor < 1) || !(o->inner_safety > 0 && o->inner_safety <= 1))
     return RVE_EINVAL;
   if (o->stress_mask < 0 || o->stress_mask > 63) return RVE_EINVAL;
+  if (o->alpha_mode != RVE_ALPHA_CV && o->alpha_mode != RVE_ALPHA_AV) return RVE_EINVAL;
   return RVE_OK;
 }
 
@@ -1290,6 +1309,7 @@ static rve_status solve_impl(const rve_grid* grid, const float* phi, const doubl
   ctx.cache = cache;
   ctx.u2_inline = mode != kSolveDefault;
   ctx.allow_graph = mode != kSolveNoAlloc;
+  ctx.alpha_av = opt->alpha_mode == RVE_ALPHA_AV ? 1 : 0;
   char* ws = (char*)workspace;
   const GridDims& g = pl.g;
   const long long n6 = 6 * g.nvox;

@@ -229,6 +229,29 @@ __global__ void k_minres_givens(MinresState* st, const double* partials, int np,
   }
 }
 
+// Lanczos three-term update when alpha comes from <v_k, A v_k> (P5 stored p = A v_k in u):
+// u_{k+1} = p - cu_v u_k - cu_vp u_{k-1} in place, per-block ||u_{k+1}||^2 partials.  Grid (blocks, nc).
+template <typename T>
+__global__ __launch_bounds__(256) void k_lanczos(T* u, const T* uk, const T* ukm1, const MinresState* st,
+                                                 long long n6, double* partials) {
+  __shared__ double red[16];
+  const int cs = blockIdx.y;
+  const MinresState& S = st[cs];
+  double acc = 0.0;
+  if (!S.finish) {
+    const T cv = (T)S.cu_v, cvp = (T)S.cu_vp;
+    const long long off = (long long)cs * n6;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n6;
+         i += (long long)gridDim.x * blockDim.x) {
+      const T v = u[off + i] - cv * uk[off + i] - cvp * ukm1[off + i];
+      u[off + i] = v;
+      acc += (double)v * (double)v;
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[(long long)cs * gridDim.x + blockIdx.x] = s;
+}
+
 // U2: d_k = cd_u u_k + cd_d1 d_{k-1} + cd_d2 d_{k-2} (written over d_{k-2}); the solution update
 // the slot's xmode schedules (x += cx d_k plus the terms deferred from the two previous iterations).
 // One 16-byte vector per thread over a grid that covers the field once (a grid-stride loop over a

@@ -374,6 +374,28 @@ def test_capped_fp64_iterate_matches_oracle(k):
     assert _rel(out["strain"].cpu().numpy()[0], ref["eps"]) < 1e-11
 
 
+@pytest.mark.parametrize("k", [5, 6])
+def test_alpha_from_operator_capped_iterate_matches_oracle(k):
+    """alpha_mode RVE_ALPHA_AV (alpha = <v_k, A v_k> after the inverse transform, separate three-term
+    update): the FP64 iterate after exactly k MINRES steps equals the oracle's, and an FP32-mixed solve
+    gives the same <sigma> as the default alpha = <v_k, C v_k>."""
+    rve = _rve()
+    n = (16, 12, 20)
+    phi = li.random_phi(n, 78, 0.3)
+    E = li.uniaxial_strain(1e-3)
+    ref = oracle.solve(n, phi, C1, E, tol=1e-14, maxit=k, C0=C_SOFT, want_sigma=False)
+    out = rve.solve(_dev(phi), C1, E[None], C_void=C_SOFT, precision=rve.FP64, tol=1e-14, max_iter=k,
+                    want_stress=False, alpha_mode=rve.ALPHA_AV)
+    assert out["status"] == rve.RVE_NOT_CONVERGED and int(out["iterations"][0]) == k
+    assert _rel(out["strain"].cpu().numpy()[0], ref["eps"]) < 1e-11
+    phi8, _ = li.octet_phase_map((32, 24, 16), 0.12)
+    d = _dev(phi8)
+    a = rve.solve(d, C1, np.eye(6)[[0, 3]], tol=1e-8, want_stress=False)
+    b = rve.solve(d, C1, np.eye(6)[[0, 3]], tol=1e-8, want_stress=False, alpha_mode=rve.ALPHA_AV)
+    assert a["status"] == 0 and b["status"] == 0
+    assert _rel(b["eff_stress"], a["eff_stress"]) < 1e-6
+
+
 def test_graph_replay_matches_direct_launches(monkeypatch):
     """Chunks of iterations replayed from a captured HIP graph give bit-identical results to direct
     launches (deterministic reductions), also when the cached graph is reused by a second solve."""
