@@ -156,7 +156,6 @@ def main():
     ap.add_argument("--cpu-warmup", type=int, default=1, help="untimed oracle MINRES iterations before them")
     ap.add_argument("--profile-steps", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--streams", type=int, default=8, help="batch workload: concurrent streams")
     ap.add_argument("--inner-floor", type=float, default=None,
                     help="FP32-mixed: relative reduction at which an inner FP32 sweep stops (library default 1e-5)")
     ap.add_argument("--precision", choices=["fp32-mixed", "fp64"], default=None,
@@ -391,7 +390,8 @@ def learned_vs_plain(d, C1, E, tol, ws, fp32_s, fp32_iters, repeats=2):
 
 
 def bench_batch(args, grids, phis, E, cfg, C1):
-    """Heterogeneous batch: every RVE with 6 unit load cases, solve_rve_batch over several streams."""
+    """Heterogeneous batch: every RVE with 6 unit load cases, one solve_rve_batch call (RVEs grouped by
+    grid, the groups' MINRES iterations in one captured graph)."""
     import torch
     import paper_2110_00733_amd as rve
     rves = [(torch.as_tensor(p, device="cuda:0"), E) for p in phis]
@@ -407,7 +407,7 @@ def bench_batch(args, grids, phis, E, cfg, C1):
     prec = rve.FP64 if cfg["precision"] == "fp64" else rve.FP32_MIXED
 
     def one():
-        return rve.solve_batch(rves, C1, n_streams=args.streams, tol=cfg["tol"], precision=prec, workspace=ws)
+        return rve.solve_batch(rves, C1, tol=cfg["tol"], precision=prec, workspace=ws)
 
     for i in range(args.warmup):
         out = one()
@@ -424,7 +424,7 @@ def bench_batch(args, grids, phis, E, cfg, C1):
         its = [r["iterations"].tolist() for r in out["results"]]
         log(f"step {i}: {1e3 * (te - ts):.1f} ms, status {out['status']}")
     total_t = sum(times)
-    cfg.update({"streams": args.streams, "per_rve_iterations": its,
+    cfg.update({"per_rve_iterations": its, "rve_grids": [list(g) for g in grids],
                 "max_rel_residual": max(float(r["rel_residual"].max()) for r in out["results"])})
     line = {"metric": "voxel-iterations/s + wall time to 1e-6 residual at 256^3, learned vs plain",
             "value": tot_vit / total_t, "unit": "voxel-iterations/s", "n_gpus": 1, "steps": args.steps,

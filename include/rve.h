@@ -55,7 +55,6 @@ enum { RVE_FP32_MIXED = 0, RVE_FP64 = 1 };
 enum { RVE_SCHEME_ROTATED = 0, RVE_SCHEME_CONTINUOUS = 1 };
 enum { RVE_NYQ_NATURAL = 0, RVE_NYQ_ZERO_ALL = 1 };
 enum { RVE_APPLY_OPERATOR = 0, RVE_APPLY_PROJECTION = 1, RVE_APPLY_STIFFNESS_ROUNDTRIP = 2 };
-enum { RVE_ALPHA_CV = 0, RVE_ALPHA_AV = 1 };
 
 typedef struct {
   int32_t n[3]; /* voxels per axis, each a length rve_supported_length() accepts */
@@ -88,16 +87,11 @@ typedef struct {
   const double* macro_stress; /* host [n_cases][6] Mandel macroscopic stress; only the stress-controlled
                            components are read (NULL: zero, e.g. uniaxial stress).  The macroscopic
                            strain's stress-controlled components are ignored.  Read during the call only */
-  int32_t alpha_mode;   /* Lanczos diagonal alpha_k of MINRES: RVE_ALPHA_CV (default) = <v_k, C v_k>, formed
-                           in the stiffness pass, equal to <v_k, A v_k> for a compatible v_k because Ghat
-                           is an orthogonal projector; RVE_ALPHA_AV = <v_k, A v_k> from the last inverse
-                           pass, which then stores A v_k and a separate pass applies the three-term
-                           Lanczos update (one more field pass per iteration, no compatibility assumed) */
 } rve_options;
 
 /* Fills *opt with the defaults: tol 1e-6, max_iter 5000, FP32_MIXED, max_refine 24, natural Nyquist,
  * rotated scheme, check_every 24, inner_floor 3e-2, inner_safety 0.9, stress_mask 0 (strain control),
- * macro_stress NULL, alpha_mode RVE_ALPHA_CV. */
+ * macro_stress NULL. */
 void rve_default_options(rve_options* opt);
 
 /* 1 if the FFT kernels provide axis length n, else 0: every n in [2, 256] without a prime factor
@@ -155,21 +149,28 @@ typedef struct {
   double* rel_residual;              /* host [n_cases] */
   const double* macro_stress;        /* host [n_cases][6] or NULL: this RVE's macroscopic stress under
                                         mixed control (replaces opt->macro_stress for this item) */
-  int32_t status;                    /* out: this RVE's solve_rve status */
+  double* mean_strain;               /* host [n_cases][6] or NULL: total macroscopic strain per case
+                                        (as rve_last_mean_strain) */
+  int32_t status;                    /* out: this RVE's status (as solve_rve's) */
 } rve_batch_item;
 
-/* Workspace for solve_rve_batch: min(n_streams, n_items) slots of the largest item's requirement. */
-size_t rve_batch_workspace_bytes(const rve_batch_item* items, int32_t n_items, const rve_options* opt,
-                                 int32_t n_streams);
+/* Workspace for solve_rve_batch: per group of RVEs with the same grid and phase stiffness, the
+ * workspace of one solve over all their load cases plus a copy of each case's phase map (and, where an
+ * item has a warm start, of the warm starts).  0 on a bad item. */
+size_t rve_batch_workspace_bytes(const rve_batch_item* items, int32_t n_items, const rve_options* opt);
 
-/* Many RVEs of uneven size (each with its own grid, phase map and load cases) solved concurrently:
- * one host worker per stream (n_streams HIP streams, all on the current device, default priority)
- * claims the largest remaining RVE, solves it on its stream with its own workspace slot, and replays
- * its own captured iteration graph; kernels of different RVEs overlap on the GPU.  All items are
- * validated before any work starts.  Returns the worst status; per-item statuses are in items[i].status.
- * The per-kernel profiler (rve_profile_*) is shared by the workers. */
+/* Many RVEs of uneven size (each with its own grid, phase map and load cases) in one solve (the batched
+ * form of eq. gallin): RVEs with equal grid and phase stiffness are grouped, and each group is one
+ * multi-case solve whose cases carry their own phase map; all groups run their FP32 sweeps and FP64
+ * refinements in lockstep, and the MINRES iterations of all groups are one captured HIP graph whose
+ * parallel branches are the groups (replayed chunk by chunk until every case of every RVE has
+ * finished; a finished case's kernels return at once).  Results equal those of solve_rve on each item
+ * (same per-case arithmetic).  All items are validated before any work starts.  Runs on hip_stream
+ * (the library's branch streams fork from it and join back); returns the worst status, per-item
+ * statuses are in items[i].status.  Differs from solve_rve in one respect: rve_last_solve_info and
+ * rve_last_mean_strain are not updated (use items[i].mean_strain). */
 rve_status solve_rve_batch(rve_batch_item* items, int32_t n_items, const rve_options* opt, void* workspace,
-                           size_t workspace_bytes, void* const* hip_streams, int32_t n_streams);
+                           size_t workspace_bytes, void* hip_stream);
 
 /* Workspace bytes rve_apply needs. */
 size_t rve_apply_workspace_bytes(const rve_grid* grid, int32_t n_cases, int32_t precision);

@@ -21,7 +21,6 @@ FP32_MIXED, FP64 = 0, 1
 ROTATED, CONTINUOUS = 0, 1
 NYQ_NATURAL, NYQ_ZERO_ALL = 0, 1
 APPLY_OPERATOR, APPLY_PROJECTION, APPLY_STIFFNESS_ROUNDTRIP = 0, 1, 2
-ALPHA_CV, ALPHA_AV = 0, 1
 
 # every symbol include/rve.h declares
 ABI_SYMBOLS = ("rve_default_options", "rve_supported_length", "rve_validate", "rve_workspace_bytes", "solve_rve",
@@ -48,8 +47,7 @@ class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("nyquist", ctypes.c_int32), ("scheme", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("inner_floor", ctypes.c_double), ("inner_safety", ctypes.c_double),
-                ("stress_mask", ctypes.c_int32), ("macro_stress", ctypes.POINTER(ctypes.c_double)),
-                ("alpha_mode", ctypes.c_int32)]
+                ("stress_mask", ctypes.c_int32), ("macro_stress", ctypes.POINTER(ctypes.c_double))]
 
 
 class BatchItem(ctypes.Structure):
@@ -58,7 +56,8 @@ class BatchItem(ctypes.Structure):
                 ("n_cases", ctypes.c_int32), ("eps0", ctypes.c_void_p), ("strain_out", ctypes.c_void_p),
                 ("stress_out", ctypes.c_void_p), ("eff_stress", ctypes.POINTER(ctypes.c_double)),
                 ("iterations", ctypes.POINTER(ctypes.c_int32)), ("rel_residual", ctypes.POINTER(ctypes.c_double)),
-                ("macro_stress", ctypes.POINTER(ctypes.c_double)), ("status", ctypes.c_int32)]
+                ("macro_stress", ctypes.POINTER(ctypes.c_double)), ("mean_strain", ctypes.POINTER(ctypes.c_double)),
+                ("status", ctypes.c_int32)]
 
 
 _lib = None
@@ -98,10 +97,9 @@ def load_library():
     lib.rve_profile_kind_name.argtypes = [ctypes.c_int32]
     lib.rve_profile_kind_name.restype = ctypes.c_char_p
     bp = ctypes.POINTER(BatchItem)
-    lib.rve_batch_workspace_bytes.argtypes = [bp, ctypes.c_int32, op, ctypes.c_int32]
+    lib.rve_batch_workspace_bytes.argtypes = [bp, ctypes.c_int32, op]
     lib.rve_batch_workspace_bytes.restype = ctypes.c_size_t
-    lib.solve_rve_batch.argtypes = [bp, ctypes.c_int32, op, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p),
-                                    ctypes.c_int32]
+    lib.solve_rve_batch.argtypes = [bp, ctypes.c_int32, op, vp, ctypes.c_size_t, vp]
     lib.solve_rve_batch.restype = ctypes.c_int
     lib.rve_autotune.argtypes = [gp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t, vp, ctypes.c_char_p, dp]
     lib.rve_autotune.restype = ctypes.c_int
@@ -363,13 +361,11 @@ def solve(phi, C_solid, macro_strain, *, C_void=None, L=(1.0, 1.0, 1.0), opt: Op
                 status=int(st))
 
 
-_batch_streams = []
-
-
-def solve_batch(rves, C_solid, *, C_void=None, n_streams: int = 8, opt: Options | None = None,
-                want_stress: bool = False, workspace: Workspace | None = None, check: bool = True, **opt_kw) -> dict:
-    """solve_rve_batch: `rves` is a list of (phi [n0,n1,n2] float32 CUDA tensor, macro strains [nc,6]),
-    grids may differ.  Returns dict(results=[per-RVE dict like solve()], status)."""
+def solve_batch(rves, C_solid, *, C_void=None, opt: Options | None = None, want_stress: bool = False,
+                workspace: Workspace | None = None, check: bool = True, **opt_kw) -> dict:
+    """solve_rve_batch: `rves` is a list of (phi [n0,n1,n2] float32 CUDA tensor, macro strains [nc,6]) or
+    (phi, macro strains, macro stresses) under mixed control; grids may differ.  Returns
+    dict(results=[per-RVE dict like solve()], status)."""
     torch = _torch()
     lib = load_library()
     opt = opt or default_options(**opt_kw)
@@ -379,7 +375,8 @@ def solve_batch(rves, C_solid, *, C_void=None, n_streams: int = 8, opt: Options 
     items = (BatchItem * len(rves))()
     results = []
     dev = rves[0][0].device
-    for i, (phi, E) in enumerate(rves):
+    for i, rv in enumerate(rves):
+        phi, E = rv[0], rv[1]
         if not (phi.is_cuda and phi.dtype == torch.float32 and phi.dim() == 3 and phi.is_contiguous()):
             raise ValueError("each phi must be a contiguous float32 CUDA tensor (n0, n1, n2)")
         E = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(-1, 6))
@@ -387,7 +384,8 @@ def solve_batch(rves, C_solid, *, C_void=None, n_streams: int = 8, opt: Options 
         nc = E.shape[0]
         r = dict(strain=torch.empty((nc, 6) + n, dtype=fdt, device=dev),
                  stress=torch.empty((nc, 6) + n, dtype=fdt, device=dev) if want_stress else None,
-                 eff_stress=np.zeros((nc, 6)), iterations=np.zeros(nc, dtype=np.int32), rel_residual=np.zeros(nc))
+                 eff_stress=np.zeros((nc, 6)), mean_strain=np.zeros((nc, 6)), iterations=np.zeros(nc, dtype=np.int32),
+                 rel_residual=np.zeros(nc))
         results.append(r)
         keep.append(E)
         it = items[i]
@@ -402,22 +400,24 @@ def solve_batch(rves, C_solid, *, C_void=None, n_streams: int = 8, opt: Options 
         it.eff_stress = _dp(r["eff_stress"])
         it.iterations = r["iterations"].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         it.rel_residual = _dp(r["rel_residual"])
-    while len(_batch_streams) < n_streams:
-        _batch_streams.append(torch.cuda.Stream(device=dev))
-    streams = (ctypes.c_void_p * n_streams)(*[s.cuda_stream for s in _batch_streams[:n_streams]])
-    nbytes = lib.rve_batch_workspace_bytes(items, len(rves), ctypes.byref(opt), n_streams)
+        it.mean_strain = _dp(r["mean_strain"])
+        if len(rv) > 2 and rv[2] is not None:
+            S = np.ascontiguousarray(np.broadcast_to(np.asarray(rv[2], dtype=np.float64).reshape(-1, 6), (nc, 6)))
+            keep.append(S)
+            it.macro_stress = _dp(S)
+    nbytes = lib.rve_batch_workspace_bytes(items, len(rves), ctypes.byref(opt))
     if nbytes == 0:
         raise RveError(RVE_EINVAL, "rve_batch_workspace_bytes")
     ws = (workspace or _default_ws).get(nbytes, dev)
     cur = torch.cuda.current_stream(dev)
-    for s_ in _batch_streams[:n_streams]:
-        s_.wait_stream(cur)
+    ss = _solver_stream(torch, dev)
+    ss.wait_stream(cur)
     st = lib.solve_rve_batch(items, len(rves), ctypes.byref(opt), ctypes.c_void_p(ws.data_ptr()),
-                             ctypes.c_size_t(ws.numel()), streams, n_streams)
-    for s_ in _batch_streams[:n_streams]:
-        cur.wait_stream(s_)
+                             ctypes.c_size_t(ws.numel()), ctypes.c_void_p(ss.cuda_stream))
+    cur.wait_stream(ss)
     for i, r in enumerate(results):
         r["status"] = int(items[i].status)
+    del keep
     if check and st < 0:
         raise RveError(st, "solve_rve_batch")
     return dict(results=results, status=int(st))

@@ -87,6 +87,7 @@ struct Material {
   // sigma = lam tr(eps) 1 + mu2 eps, with 1 = (1,1,1,0,0,0)
   int iso_d, iso_0;
   T lam_d, mu2_d, lam_0, mu2_0;
+  long long phi_stride;  // voxels between the phase maps of consecutive load cases (0: one map for all)
 };
 
 // x when A, else y (references of possibly different types, chosen at compile time)
@@ -226,6 +227,7 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
   const T xs = xscale_ib ? (T)xscale_ib[(long long)cs * xscale_stride] : (T)1;
   const long long row = ((long long)n0 * g.n1 + n1) * N;
   const T* xc = x + (long long)cs * 6 * g.nvox;
+  const float* phic = phi + (long long)cs * mat.phi_stride;
   __shared__ double red[16];
   double acc = 0.0;
 
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
     T e[6][NA], ph[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      ph[i] = (row_ok && mat.use_phi) ? (T)phi[row + t + NB * i] : (T)0;
+      ph[i] = (row_ok && mat.use_phi) ? (T)phic[row + t + NB * i] : (T)0;
 #pragma unroll
       for (int c = 0; c < 6; ++c) e[c][i] = row_ok ? xc[c * g.nvox + row + t + NB * i] : (T)0;
     }
@@ -916,13 +918,11 @@ __global__ __launch_bounds__(192) void k_axis0_project_split3(cx<T>* __restrict_
 // grid (ceil(N1/W), N0, ncases), block W*NB threads, dyn. LDS W*max(NA*(NB+1), N+1) complex
 // Lanczos mode (uk != nullptr, MINRES iterations): the transform output p = A v_k is never stored;
 // instead y = u_{k+1} = p - cu_v u_k - cu_vp u_{k-1} is written with per-block ||u_{k+1}||^2 partials.
-// With av = 1 (alpha taken as <v_k, A v_k>): y = p is stored and the partials are <p, u_k>; the
-// three-term update then runs as k_lanczos once alpha is known.
 template <typename T, int NA, int NB>
 __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spec, T* __restrict__ y,
                                                    const T* __restrict__ uk, const T* __restrict__ ukm1,
                                                    double* partials, const cx<T>* __restrict__ tw, GridDims g, int W,
-                                                   const MinresState* __restrict__ st, int av) {
+                                                   const MinresState* __restrict__ st) {
   constexpr int N = NA * NB;
   constexpr int TT = NB;
   constexpr int CB = (NA + TT - 1) / TT;
@@ -944,7 +944,7 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
   const bool lz = uk != nullptr;
   const T* uc = lz ? uk + (long long)cs * 6 * g.nvox : nullptr;
   const T* umc = lz ? ukm1 + (long long)cs * 6 * g.nvox : nullptr;
-  const T cv = lz ? (av ? (T)1 : (T)st[cs].cu_v) : (T)0, cvp = (lz && !av) ? (T)st[cs].cu_vp : (T)0;
+  const T cv = lz ? (T)st[cs].cu_v : (T)0, cvp = lz ? (T)st[cs].cu_vp : (T)0;
   double acc = 0.0;
   // spectrum components this thread gathers, one pair ahead of the transform that uses them
   constexpr int LK = (N / 2 + 1 + TT - 1) / TT;
@@ -975,8 +975,7 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const long long oo = (2 * p2 + h) * g.nvox + o;
-            dvs[DV_AHEAD ? p2 : 0][j][b][h] =
-                (CB == 1 || a < NA) ? (av ? uc[oo] : cv * uc[oo] + cvp * umc[oo]) : (T)0;
+            dvs[DV_AHEAD ? p2 : 0][j][b][h] = (CB == 1 || a < NA) ? cv * uc[oo] + cvp * umc[oo] : (T)0;
           }
         }
       }
@@ -1001,7 +1000,7 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
               const long long oo = (2 * pr + h) * g.nvox + o;
-              dvl[j][b][h] = (CB == 1 || a < NA) ? (av ? uc[oo] : cv * uc[oo] + cvp * umc[oo]) : (T)0;
+              dvl[j][b][h] = (CB == 1 || a < NA) ? cv * uc[oo] + cvp * umc[oo] : (T)0;
             }
           }
         }
@@ -1049,9 +1048,7 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
           for (int b = 0; b < NB; ++b) {
             const long long o = row + a + NA * b;
             T r0 = yb[b].re, r1 = yb[b].im;
-            if (lz && av) {
-              acc += (double)r0 * (double)dv[j][b][0] + (double)r1 * (double)dv[j][b][1];
-            } else if (lz) {
+            if (lz) {
               r0 -= dv[j][b][0];
               r1 -= dv[j][b][1];
               acc += (double)r0 * (double)r0 + (double)r1 * (double)r1;

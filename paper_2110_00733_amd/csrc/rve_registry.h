@@ -13,7 +13,7 @@ template <typename T>
 using P3Fn = void (*)(cx<T>*, const cx<T>*, FreqTables<T>, GridDims, int, T, const MinresState*);
 template <typename T>
 using P5Fn = void (*)(const cx<T>*, T*, const T*, const T*, double*, const cx<T>*, GridDims, int,
-                      const MinresState*, int);
+                      const MinresState*);
 
 template <typename T>
 struct LenKernels {

@@ -19,7 +19,6 @@
 #include <cstdlib>
 #include <atomic>
 #include <mutex>
-#include <thread>
 #include <vector>
 
 #include "../../include/rve.h"
@@ -444,7 +443,7 @@ template <typename T>
 static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, const float* phi,
                      const Material<T>& mat, const Tables<T>& tb, cx<T>* spec, T* y, const T* uk, const T* ukm1,
                      double* partials, MinresState* st, int identity, hipStream_t s, int u2_slot = 0,
-                     hipEvent_t before_p5 = nullptr, hipEvent_t after_p2 = nullptr, int alpha_av = 0) {
+                     hipEvent_t before_p5 = nullptr, hipEvent_t after_p2 = nullptr) {
   constexpr int el = (int)sizeof(T);
   const LenKernels<T>& K0 = axis(pl, el, 0)->k<T>();
   const LenKernels<T>& K1 = axis(pl, el, 1)->k<T>();
@@ -468,9 +467,9 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     dim3 grid((g.n1 + W - 1) / W, g.n0, nc);
     prof::begin<T>(prof::P1, s);
     hipLaunchKernelGGL(K2.p1, grid, dim3(W * nb2), lds, s, x, xscale, (int)(sizeof(MinresState) / sizeof(double)),
-                       phi, mat, spec, tb.tw[2], g, W, st, (uk && !alpha_av) ? partials : nullptr);
+                       phi, mat, spec, tb.tw[2], g, W, st, uk ? partials : nullptr);
     prof::end(s);
-    if (uk && !alpha_av) {
+    if (uk) {
       prof::begin<T>(prof::S1, s);
       hipLaunchKernelGGL(k_minres_alpha, dim3(nc), dim3(256), 0, s, st, partials, (int)(grid.x * grid.y));
     }
@@ -525,24 +524,12 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     // P5 overwrites the field an earlier iteration's U2 (second stream) may still be reading
     if (before_p5) (void)hipStreamWaitEvent(s, before_p5, 0);
     prof::begin<T>(prof::P5, s);
-    hipLaunchKernelGGL(K2.p5, grid, dim3(W * nb2), lds, s, spec, y, uk, ukm1, partials, tb.tw[2], g, W, st,
-                       alpha_av);
+    hipLaunchKernelGGL(K2.p5, grid, dim3(W * nb2), lds, s, spec, y, uk, ukm1, partials, tb.tw[2], g, W, st);
     prof::end(s);
-    int np2 = (int)(grid.x * grid.y);
-    if (uk && alpha_av) {
-      // alpha = <v_k, A v_k> from P5's partials, then the three-term update on the stored A v_k
-      prof::begin<T>(prof::S1, s);
-      hipLaunchKernelGGL(k_minres_alpha, dim3(nc), dim3(256), 0, s, st, partials, np2);
-      prof::end(s);
-      prof::begin<T>(prof::P5, s);  // timed as part of the inverse-transform + Lanczos step
-      hipLaunchKernelGGL(k_lanczos<T>, dim3(kRedBlocks, nc), dim3(kThreads), 0, s, y, uk, ukm1, st, 6 * g.nvox,
-                         partials);
-      prof::end(s);
-      np2 = kRedBlocks;
-    }
     if (uk) {
       prof::begin<T>(prof::S2, s);
-      hipLaunchKernelGGL(k_minres_givens, dim3(nc), dim3(256), 0, s, st, partials, np2, u2_slot);
+      hipLaunchKernelGGL(k_minres_givens, dim3(nc), dim3(256), 0, s, st, partials, (int)(grid.x * grid.y),
+                         u2_slot);
     }
     prof::end(s);
   }
@@ -579,8 +566,8 @@ struct ChunkGraph {
   hipGraph_t graph = nullptr;
   std::vector<unsigned char> key;
   void reset() {
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     exec = nullptr;
     graph = nullptr;
     key.clear();
@@ -588,25 +575,39 @@ struct ChunkGraph {
 };
 
 // Resources kept between solves, one set per (device, solve stream): the U2 side stream and its
-// events, and the captured chunk graphs ([0] FP32 fields, [1] FP64 fields).  A batch reuses the
-// caller's streams call after call, so repeated batches find their sets again instead of creating new
-// ones.  A set is owned by one solve at a time (a second concurrent solve on the same stream gets a set
-// of its own).  Everything is freed by rve_release_caches().
+// events, the captured chunk graphs ([0] FP32 fields, [1] FP64 fields), and for batches the branch
+// streams, fork/join events and the lockstep graph of all solves of the batch.  Repeated calls on the
+// same stream find their set again instead of creating new objects.  A set is owned by one solve at a
+// time (a second concurrent solve on the same stream gets a set of its own).  Everything is freed by
+// rve_release_caches().
+constexpr int kBranchStreams = 64;  // parallel branches of a batch graph (one per solve up to this many)
 struct StreamCache {
   int dev = 0;
   hipStream_t stream = nullptr;
   bool busy = false;
   U2Side u2;
   ChunkGraph graph[2];
+  std::vector<hipStream_t> branch;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  ChunkGraph multi[2];
   void release() {
     graph[0].reset();
     graph[1].reset();
-    for (hipEvent_t e : u2.after_p2) hipEventDestroy(e);
-    for (hipEvent_t e : u2.after_u2) hipEventDestroy(e);
+    multi[0].reset();
+    multi[1].reset();
+    for (hipEvent_t e : u2.after_p2) (void)hipEventDestroy(e);
+    for (hipEvent_t e : u2.after_u2) (void)hipEventDestroy(e);
     u2.after_p2.clear();
     u2.after_u2.clear();
-    if (u2.s2) hipStreamDestroy(u2.s2);
+    if (u2.s2) (void)hipStreamDestroy(u2.s2);
     u2.s2 = nullptr;
+    for (hipStream_t b : branch) (void)hipStreamDestroy(b);
+    branch.clear();
+    for (hipEvent_t e : join) (void)hipEventDestroy(e);
+    join.clear();
+    if (fork) (void)hipEventDestroy(fork);
+    fork = nullptr;
   }
 };
 static std::mutex g_cache_mu;
@@ -645,7 +646,6 @@ struct LoopCtx {
   StreamCache* cache = nullptr;  // nullptr: U2 inline on the solve stream, no graph
   bool u2_inline = false;        // batch workers and profiled solves keep U2 on the solve stream
   bool allow_graph = true;
-  int alpha_av = 0;              // alpha = <v, A v> after P5 instead of <v, C v> in P1 (RVE_ALPHA_AV)
 };
 
 static rve_status u2_events(U2Side& U, int count, bool need_stream) {
@@ -666,7 +666,7 @@ static rve_status u2_events(U2Side& U, int count, bool need_stream) {
 template <typename T>
 static rve_status enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, const float* phi,
                                      const Material<T>& mat, const Tables<T>& tb, cx<T>* spec, MinresState* st,
-                                     double* part, int count, int ph[5], hipStream_t s, U2Side* U, int alpha_av) {
+                                     double* part, int count, int ph[5], hipStream_t s, U2Side* U) {
   const long long n6 = 6 * pl.g.nvox;
   dim3 vg, vb;
   vec_grid(nc, &vg, &vb);
@@ -689,8 +689,7 @@ static rve_status enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, c
   };
   if (!U) {
     for (int j = 0; j < count; ++j) {
-      apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s, j & 1,
-                  nullptr, nullptr, alpha_av);
+      apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s, j & 1);
       launch_u2(s, j, id2, id1, ib);
       const int t0 = ia;
       ia = ib;
@@ -713,7 +712,7 @@ static rve_status enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, c
     // iteration j's operator; U2(j-1) starts when P2(j) is done and streams beside P3(j), the pass
     // that leaves the most bandwidth unused
     apply_op<T>(pl, nc, B.u[ib], &st[0].ib, phi, mat, tb, spec, B.u[ic], B.u[ib], B.u[ia], part, st, 0, s, j & 1,
-                j >= 2 ? U->after_u2[j - 2] : nullptr, j >= 1 ? U->after_p2[j] : nullptr, alpha_av);
+                j >= 2 ? U->after_u2[j - 2] : nullptr, j >= 1 ? U->after_p2[j] : nullptr);
     if (j >= 1) {
       const rve_status r2 = u2(j - 1, prev[0], prev[1], prev[2], U->after_p2[j]);
       if (r2 != RVE_OK) return r2;
@@ -739,8 +738,7 @@ static rve_status enqueue_iterations(const Plan& pl, int nc, MinresBufs<T>& B, c
 template <typename T>
 static std::vector<unsigned char> chunk_key(const Plan& pl, int nc, const MinresBufs<T>& B, const float* phi,
                                             const Material<T>& mat, const Tables<T>& tb, const cx<T>* spec,
-                                            const MinresState* st, const double* part, int chunk, bool inl,
-                                            int alpha_av) {
+                                            const MinresState* st, const double* part, int chunk, bool inl) {
   std::vector<unsigned char> k;
   auto put = [&](const void* p, size_t n) {
     const unsigned char* c = static_cast<const unsigned char*>(p);
@@ -759,7 +757,6 @@ static std::vector<unsigned char> chunk_key(const Plan& pl, int nc, const Minres
   put(&part, sizeof(part));
   put(&chunk, sizeof(chunk));
   put(&inl, sizeof(inl));  // the captured graph has U2 on a side stream or inline
-  put(&alpha_av, sizeof(alpha_av));
   return k;
 }
 
@@ -790,14 +787,13 @@ static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const fl
   bool use_graph = ctx.cache && ctx.allow_graph && graphs_enabled() && !prof::on && s != nullptr;
   ChunkGraph* G = use_graph ? &ctx.cache->graph[sizeof(T) == 8 ? 1 : 0] : nullptr;
   if (use_graph) {
-    std::vector<unsigned char> key = chunk_key<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk, inl, ctx.alpha_av);
+    std::vector<unsigned char> key = chunk_key<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk, inl);
     if (G->exec == nullptr || G->key != key) {
       G->reset();
       int ph[5] = {0, 1, 2, 0, 1};
       bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
-        const rve_status er =
-            enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk, ph, s, U, ctx.alpha_av);
+        const rve_status er = enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, chunk, ph, s, U);
         const hipError_t le = hipGetLastError();
         hipGraph_t gr = nullptr;
         ok = hipStreamEndCapture(s, &gr) == hipSuccess && le == hipSuccess && gr != nullptr && er == RVE_OK;
@@ -825,7 +821,7 @@ static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const fl
       it += chunk;
     } else {
       const int n = std::min(check, max_iter - it);
-      const rve_status er = enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, n, ph, s, U, ctx.alpha_av);
+      const rve_status er = enqueue_iterations<T>(pl, nc, B, phi, mat, tb, spec, st, part, n, ph, s, U);
       if (er != RVE_OK) return er;
       it += n;
     }
@@ -836,6 +832,481 @@ static rve_status minres_loop(const Plan& pl, int nc, MinresBufs<T>& B, const fl
     bool all = true;
     for (int c = 0; c < nc; ++c) all = all && hs[c].finish;
     if (all) break;
+  }
+  return RVE_OK;
+}
+
+// ---------------------------------------------------------------------------- one solve, in phases
+// The work of a solve_rve call (n_cases load cases on one grid and material), split into the phases a
+// heterogeneous batch runs in lockstep over many such solves: setup (phase-map check, tables, right-hand
+// side, start), sweeps (an MINRES run from the current FP64 residual, then the refinement bookkeeping)
+// and post-processing.  The load cases may each have their own phase map (mat.phi_stride voxels apart).
+struct SolveRun {
+  const rve_grid* grid = nullptr;
+  const float* phi = nullptr;
+  const double* C = nullptr;
+  const rve_options* opt = nullptr;
+  int nc = 0, prec = 0;
+  Plan pl;
+  Layout L;
+  char* ws = nullptr;
+  hipStream_t s = nullptr;
+  long long n6 = 0, phi_count = 0;
+  MinresState* dst = nullptr;
+  CaseInfo* dci = nullptr;
+  double *part = nullptr, *sums = nullptr, *Ed2 = nullptr;
+  int* flag = nullptr;
+  double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr, *t64 = nullptr;
+  cx<double>* spec64 = nullptr;
+  cx<float>* spec32 = nullptr;
+  Tables<double> tb64;
+  Tables<float> tb32;
+  Material<double> mat64, ident64;
+  Material<float> mat32;
+  MinresBufs<float> B32;
+  MinresBufs<double> B64;
+  std::vector<double> hE, hS;
+  std::vector<CaseInfo> hci;
+  dim3 vg, vb;
+
+  template <typename T>
+  MinresBufs<T>& bufs() {
+    if constexpr (sizeof(T) == 8) return B64;
+    else return B32;
+  }
+  template <typename T>
+  const Material<T>& mat() const {
+    if constexpr (sizeof(T) == 8) return mat64;
+    else return mat32;
+  }
+  template <typename T>
+  const Tables<T>& tables() const {
+    if constexpr (sizeof(T) == 8) return tb64;
+    else return tb32;
+  }
+  template <typename T>
+  cx<T>* spec() const {
+    if constexpr (sizeof(T) == 8) return spec64;
+    else return spec32;
+  }
+
+  // Carve the workspace and stage the per-case macroscopic loads (host only, no HIP call).
+  // macro_stress: [nc][6] or NULL.  phi_stride: voxels between consecutive cases' phase maps (0: shared).
+  rve_status init(const rve_grid* grid_, const float* phi_, long long phi_stride, const double* C_,
+                  const double* macro_strain, const double* macro_stress, int nc_, const rve_options* opt_,
+                  char* ws_, size_t ws_bytes, hipStream_t s_) {
+    grid = grid_;
+    phi = phi_;
+    C = C_;
+    opt = opt_;
+    nc = nc_;
+    prec = opt->precision;
+    ws = ws_;
+    s = s_;
+    if (!make_plan(grid, &pl)) return RVE_EUNSUPPORTED_SIZE;
+    L = make_layout(pl, nc, prec, true);
+    if ((long long)ws_bytes < L.total) return RVE_ENOMEM;
+    const GridDims& g = pl.g;
+    n6 = 6 * g.nvox;
+    phi_count = phi_stride ? (long long)nc * phi_stride : g.nvox;
+    dst = reinterpret_cast<MinresState*>(ws + L.off_state);
+    dci = reinterpret_cast<CaseInfo*>(ws + L.off_info);
+    part = reinterpret_cast<double*>(ws + L.off_part);
+    sums = reinterpret_cast<double*>(ws + L.off_sums);
+    flag = reinterpret_cast<int*>(ws + L.off_flag);
+    x64 = reinterpret_cast<double*>(ws + L.off_x64);
+    b64 = reinterpret_cast<double*>(ws + L.off_b64);
+    r64 = reinterpret_cast<double*>(ws + L.off_r64);
+    t64 = reinterpret_cast<double*>(ws + L.off_t64);
+    spec64 = reinterpret_cast<cx<double>*>(ws + L.off_spec64);
+    Ed2 = sums;  // 6 nc doubles of the 16 nc
+    mat64 = make_material<double>(C, C + 36);
+    mat32 = make_material<float>(C, C + 36);
+    mat64.phi_stride = mat32.phi_stride = phi_stride;
+    memset(&ident64, 0, sizeof(ident64));  // projection material: C = identity independent of phi
+    for (int i = 0; i < 6; ++i) ident64.C0[i * 7] = 1.0;
+    ident64.has_c0 = 1;
+    ident64.use_phi = 0;
+    if (prec == RVE_FP32_MIXED) {
+      for (int i = 0; i < 3; ++i) B32.u[i] = reinterpret_cast<float*>(ws + L.off_u32[i]);
+      for (int i = 0; i < 2; ++i) B32.d[i] = reinterpret_cast<float*>(ws + L.off_d32[i]);
+      B32.x = reinterpret_cast<float*>(ws + L.off_x32);
+      spec32 = reinterpret_cast<cx<float>*>(ws + L.off_spec32);
+    } else {
+      for (int i = 0; i < 3; ++i) B64.u[i] = reinterpret_cast<double*>(ws + L.off_u64[i]);
+      for (int i = 0; i < 2; ++i) B64.d[i] = reinterpret_cast<double*>(ws + L.off_d64[i]);
+      B64.x = x64;
+    }
+    // Mixed macroscopic control (eq. galop, eq. gallin): the macroscopic strain acts on the
+    // strain-controlled components only, the macroscopic stress on the stress-controlled ones
+    hE.assign(6 * nc, 0.0);
+    hS.assign(6 * nc, 0.0);
+    for (int c = 0; c < nc; ++c)
+      for (int a = 0; a < 6; ++a) {
+        const bool stress_ctl = (opt->stress_mask >> a) & 1;
+        hE[c * 6 + a] = stress_ctl ? 0.0 : macro_strain[c * 6 + a];
+        if (stress_ctl && macro_stress) hS[c * 6 + a] = macro_stress[c * 6 + a];
+      }
+    vec_grid(nc, &vg, &vb);
+    return RVE_OK;
+  }
+
+  // Phase maps in [0, 1] and finite (device pre-pass; synchronises the stream).
+  rve_status check_phi() {
+    HIPCHK(hipMemsetAsync(flag, 0, 64, s));
+    hipLaunchKernelGGL(k_check_phi, dim3(256), dim3(256), 0, s, phi, phi_count, flag);
+    int hflag[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hflag[0]) return RVE_ENONFINITE;
+    if (hflag[1]) return RVE_EINVAL;
+    return RVE_OK;
+  }
+
+  // Tables, right-hand side b = -A(Ebar) + Ghat(0) Sbar with ||b||, and the start x64 (zero or the
+  // projected warm start eps0 [nc][6][N] in the solve's field type), r64 = b - A x64.
+  rve_status setup(const void* eps0) {
+    const GridDims& g = pl.g;
+    rve_status r = build_tables<double>(pl, grid, ws + L.off_tab64, opt->scheme, opt->nyquist, s);
+    if (r != RVE_OK) return r;
+    tb64 = tables_at<double>(pl, ws + L.off_tab64);
+    tb64.stress_mask = opt->stress_mask;
+    if (prec == RVE_FP32_MIXED) {
+      r = build_tables<float>(pl, grid, ws + L.off_tab32, opt->scheme, opt->nyquist, s);
+      if (r != RVE_OK) return r;
+      tb32 = tables_at<float>(pl, ws + L.off_tab32);
+      tb32.stress_mask = opt->stress_mask;
+    }
+    // macro strains live in the partials buffer's head while b is formed
+    double* Ed = part;
+    double* Sd = sums + 8 * nc;  // 6 nc doubles of the 16 nc
+    HIPCHK(hipMemcpyAsync(Ed, hE.data(), sizeof(double) * 6 * nc, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(Sd, hS.data(), sizeof(double) * 6 * nc, hipMemcpyHostToDevice, s));
+    // b = -A(Ebar) + Ghat(0) Sbar  (FP64 operator; a uniform Sbar transforms to xi = 0 only, where the
+    // projection keeps its stress-controlled components), and ||b||
+    hipLaunchKernelGGL(k_fill_const<double>, vg, vb, 0, s, x64, Ed, g.nvox);
+    apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, nullptr, 0, s);
+    hipLaunchKernelGGL(k_rhs, vg, vb, 0, s, b64, r64, Sd, g.nvox, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums, 1, 1);
+    hci.assign(nc, CaseInfo{});
+    std::vector<double> hb(nc);
+    HIPCHK(hipMemcpyAsync(hb.data(), sums, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double cn = 0;
+    for (int i = 0; i < 36; ++i) cn = std::max(cn, std::fabs(C[36 + i]));
+    for (int c = 0; c < nc; ++c) {
+      hci[c].bnorm = hb[c];
+      hci[c].rnorm = hb[c];
+      hci[c].iters = 0;
+      hci[c].status = 0;
+      hci[c].warm_rejected = 0;
+      hci[c].r0 = hb[c];
+      hci[c].active = 1;
+      // A right-hand side at the rounding level of the transforms of a constant field counts as zero:
+      // the homogeneous case, answered exactly by eps = 0.
+      double en = 0, sn = 0;
+      for (int i = 0; i < 6; ++i) en = std::max(en, std::fabs(hE[c * 6 + i]));
+      for (int i = 0; i < 6; ++i) sn = std::max(sn, std::fabs(hS[c * 6 + i]));
+      const double scale = (cn * en + sn) * std::sqrt((double)n6);
+      if (hci[c].bnorm <= 1e-13 * scale) {
+        hci[c].bnorm = 0.0;
+        hci[c].active = 0;
+      }
+    }
+    HIPCHK(hipMemcpyAsync(dci, hci.data(), sizeof(CaseInfo) * nc, hipMemcpyHostToDevice, s));
+    // re-upload Ebar (part was overwritten by the norm partials)
+    HIPCHK(hipMemcpyAsync(Ed2, hE.data(), sizeof(double) * 6 * nc, hipMemcpyHostToDevice, s));
+    if (eps0) {
+      // x64 = Ghat eps0 (projection, C = identity); a start that does not lower the residual below
+      // ||b|| is dropped (k_warm_fallback)
+      if (prec == RVE_FP32_MIXED)
+        hipLaunchKernelGGL((k_lincomb<float, double>), vg, vb, 0, s, r64, (const float*)eps0, 1.0,
+                           (const double*)nullptr, 0.0, n6, part);
+      else
+        hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, (const double*)eps0, 1.0,
+                           (const double*)nullptr, 0.0, n6, part);
+      apply_op<double>(pl, nc, r64, nullptr, phi, ident64, tb64, spec64, x64, nullptr, nullptr, nullptr, nullptr, 0,
+                       s);
+      apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, nullptr, 0, s);
+      hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
+      hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
+      hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
+                         opt->max_iter);
+      hipLaunchKernelGGL(k_warm_fallback, dim3(1024, nc), dim3(256), 0, s, x64, r64, b64, dci, n6);
+      hipLaunchKernelGGL(k_residual_update_fallback, dim3((nc + 63) / 64), dim3(64), 0, s, dci, nc);
+    } else {
+      hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, x64, n6 * nc);
+      HIPCHK(hipMemcpyAsync(r64, b64, sizeof(double) * n6 * nc, hipMemcpyDeviceToDevice, s));
+    }
+    HIPCHK(hipGetLastError());
+    return RVE_OK;
+  }
+
+  // Start an MINRES run on A d = r64 for the cases still active (FP32_MIXED: a sweep, u_1 = fp32(r64);
+  // FP64: the one run, on A x = b from x64).  *any: some case of this solve runs (read from the device,
+  // which synchronises); with any == nullptr the run is launched without that check (cases that are
+  // not active finish at once).
+  rve_status sweep_begin(bool* any) {
+    if (any) {
+      HIPCHK(hipMemcpyAsync(hci.data(), dci, sizeof(CaseInfo) * nc, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      *any = false;
+      for (int c = 0; c < nc; ++c) *any = *any || hci[c].active;
+    }
+    if (prec == RVE_FP32_MIXED) {
+      if (any && !*any) return RVE_OK;
+      // u_1 = fp32(r64), u_0 = d = x32 = 0
+      hipLaunchKernelGGL((k_lincomb<double, float>), vg, vb, 0, s, B32.u[1], r64, 1.0, (const double*)nullptr, 0.0,
+                         n6, part);
+      hipLaunchKernelGGL(k_minres_init, dim3(nc), dim3(kThreads), 0, s, dst, part, kRedBlocks, dci, opt->tol,
+                         opt->inner_safety, opt->inner_floor, opt->max_iter);
+      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B32.u[0], n6 * nc);
+      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B32.d[0], n6 * nc);
+      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B32.d[1], n6 * nc);
+      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B32.x, n6 * nc);
+    } else {
+      // FP64: one MINRES on A x = b from the start x64 (r64 = b - A x64); inactive cases finish at once
+      hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, B64.u[1], r64, 1.0, (const double*)nullptr, 0.0,
+                         n6, part);
+      hipLaunchKernelGGL(k_minres_init, dim3(nc), dim3(kThreads), 0, s, dst, part, kRedBlocks, dci, opt->tol, 1.0,
+                         1e-300, opt->max_iter);
+      hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, B64.u[0], n6 * nc);
+      hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, B64.d[0], n6 * nc);
+      hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, B64.d[1], n6 * nc);
+    }
+    HIPCHK(hipGetLastError());
+    return RVE_OK;
+  }
+
+  // After an MINRES run: count its iterations, update x64 (FP32_MIXED: x64 += x32, re-projected onto
+  // compatible fields), recompute the FP64 residual r64 = b - A x64 and decide which cases go on.
+  rve_status sweep_end() {
+    hipLaunchKernelGGL(k_sweep_done, dim3((nc + 63) / 64), dim3(64), 0, s, dst, dci, nc);
+    if (prec == RVE_FP32_MIXED) {
+      hipLaunchKernelGGL(k_accum<float>, vg, vb, 0, s, x64, B32.x, n6, (const int*)nullptr);
+      // The exact fluctuation is compatible and has zero mean.  FP32 rounding inside the sweep leaves
+      // incompatible components (a mean among them) that the projected residual cannot see but the
+      // average stress does: project the FP64 iterate back onto compatible fields.
+      apply_op<double>(pl, nc, x64, nullptr, phi, ident64, tb64, spec64, t64, nullptr, nullptr, nullptr, nullptr, 0,
+                       s);
+      hipLaunchKernelGGL(k_keep_inactive, dim3(1024, nc), dim3(256), 0, s, t64, x64, dci, n6);
+      std::swap(x64, t64);
+    }
+    apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, nullptr, 0, s);
+    hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
+    hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
+                       opt->max_iter);
+    HIPCHK(hipGetLastError());
+    return RVE_OK;
+  }
+
+  // Post-processing of cases [c0, c0 + ncs): strain/stress fields into the caller's buffers
+  // ([ncs][6][N]), <sigma>, iterations, FP64 residuals, total macroscopic strain; returns the worst
+  // status over those cases.  Synchronises.
+  rve_status post(int c0, int ncs, void* strain_out, void* stress_out, double* eff_stress, int32_t* iterations,
+                  double* rel_residual, double* mean_strain, rve_status* worst) {
+    const GridDims& g = pl.g;
+    const float* phic = phi + (long long)c0 * mat64.phi_stride;
+    const double* xc = x64 + (long long)c0 * n6;
+    if (prec == RVE_FP32_MIXED)
+      hipLaunchKernelGGL(k_post<float>, dim3(kRedBlocks, ncs), dim3(kThreads), 0, s, xc, phic, mat64, Ed2 + 6 * c0,
+                         (float*)strain_out, (float*)stress_out, g.nvox, part);
+    else
+      hipLaunchKernelGGL(k_post<double>, dim3(kRedBlocks, ncs), dim3(kThreads), 0, s, xc, phic, mat64, Ed2 + 6 * c0,
+                         (double*)strain_out, (double*)stress_out, g.nvox, part);
+    // r64 is free now: it holds the sums
+    hipLaunchKernelGGL(k_sum_partials, dim3(6 * ncs), dim3(kThreads), 0, s, part, kRedBlocks, r64, 1, 0);
+    hipLaunchKernelGGL(k_field_sums, dim3(kRedBlocks, ncs), dim3(kThreads), 0, s, xc, g.nvox, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(6 * ncs), dim3(kThreads), 0, s, part, kRedBlocks, r64 + 6 * ncs, 1, 0);
+    std::vector<double> hs(12 * ncs);
+    HIPCHK(hipMemcpyAsync(hs.data(), r64, sizeof(double) * 12 * ncs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hci.data(), dci, sizeof(CaseInfo) * nc, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    rve_status worst_err = RVE_OK, worst_warn = RVE_OK;
+    for (int k = 0; k < ncs; ++k) {
+      const CaseInfo& ci = hci[c0 + k];
+      for (int a = 0; a < 6; ++a) eff_stress[k * 6 + a] = hs[k * 6 + a] / (double)g.nvox;
+      if (mean_strain)
+        for (int a = 0; a < 6; ++a)
+          mean_strain[k * 6 + a] = hE[(c0 + k) * 6 + a] + hs[6 * ncs + k * 6 + a] / (double)g.nvox;
+      iterations[k] = ci.iters;
+      rel_residual[k] = ci.bnorm > 0 ? ci.rnorm / ci.bnorm : 0.0;
+      if (ci.status == RVE_ENONFINITE || !std::isfinite(rel_residual[k])) worst_err = RVE_ENONFINITE;
+      else if (ci.status == RVE_BREAKDOWN) worst_warn = RVE_BREAKDOWN;
+      else if (ci.bnorm > 0 && !(rel_residual[k] <= opt->tol) && worst_warn == RVE_OK) worst_warn = RVE_NOT_CONVERGED;
+    }
+    *worst = worst_err != RVE_OK ? worst_err : worst_warn;
+    return RVE_OK;
+  }
+};
+
+// MINRES iterations of many solves at once: one captured graph whose parallel branches (fork from the
+// solve stream onto the cache's branch streams, join back) each run one solve's chunk of iterations.
+// After every replay each solve whose cases have all finished their MINRES run is refined at once
+// (FP64 residual, next FP32 sweep started), independently of the others, and rejoins the next replay:
+// a chunk always starts from the same buffer phase, so a restarted solve fits the captured graph.  A
+// solve that is converged (or out of sweeps or iterations) leaves the graph when the graph is next
+// captured, which happens once such solves make up half of it.  U2 runs inline in each branch.
+// `count` iterations of every solve in `runs`, each on a branch stream, forked from and joined to `on`.
+template <typename T>
+static rve_status enqueue_multi(std::vector<SolveRun*>& runs, int count, hipStream_t on, StreamCache* cache) {
+  const int nr = (int)runs.size();
+  const int nbr = std::min(nr, kBranchStreams);
+  HIPCHK(hipEventRecord(cache->fork, on));
+  for (int b = 0; b < nbr; ++b) HIPCHK(hipStreamWaitEvent(cache->branch[b], cache->fork, 0));
+  for (int r = 0; r < nr; ++r) {
+    SolveRun& R = *runs[r];
+    int ph[5] = {0, 1, 2, 0, 1};
+    const rve_status er = enqueue_iterations<T>(R.pl, R.nc, R.bufs<T>(), R.phi, R.mat<T>(), R.tables<T>(), R.spec<T>(),
+                                                R.dst, R.part, count, ph, cache->branch[r % nbr], nullptr);
+    if (er != RVE_OK) return er;
+  }
+  for (int b = 0; b < nbr; ++b) {
+    HIPCHK(hipEventRecord(cache->join[b], cache->branch[b]));
+    HIPCHK(hipStreamWaitEvent(on, cache->join[b], 0));
+  }
+  return RVE_OK;
+}
+
+template <typename T>
+static rve_status capture_multi(std::vector<SolveRun*>& runs, int chunk, hipStream_t s, StreamCache* cache,
+                                bool* use_graph) {
+  const int nr = (int)runs.size();
+  const int nbr = std::min(nr, kBranchStreams);
+  while ((int)cache->branch.size() < nbr) {
+    hipStream_t b = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+    cache->branch.push_back(b);
+  }
+  if (!cache->fork) HIPCHK(hipEventCreateWithFlags(&cache->fork, hipEventDisableTiming));
+  while ((int)cache->join.size() < nbr) {
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    cache->join.push_back(e);
+  }
+  *use_graph = graphs_enabled() && !prof::on && s != nullptr;
+  if (!*use_graph) return RVE_OK;
+  ChunkGraph& G = cache->multi[sizeof(T) == 8 ? 1 : 0];
+  std::vector<unsigned char> key;
+  for (SolveRun* R : runs) {
+    const std::vector<unsigned char> k = chunk_key<T>(R->pl, R->nc, R->bufs<T>(), R->phi, R->mat<T>(), R->tables<T>(),
+                                                      R->spec<T>(), R->dst, R->part, chunk, true);
+    key.insert(key.end(), k.begin(), k.end());
+  }
+  if (G.exec != nullptr && G.key == key) return RVE_OK;
+  G.reset();
+  bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    const rve_status er = enqueue_multi<T>(runs, chunk, s, cache);
+    const hipError_t le = hipGetLastError();
+    hipGraph_t gr = nullptr;
+    ok = hipStreamEndCapture(s, &gr) == hipSuccess && le == hipSuccess && gr != nullptr && er == RVE_OK;
+    if (ok) {
+      G.graph = gr;
+      ok = hipGraphInstantiate(&G.exec, gr, nullptr, nullptr, 0) == hipSuccess;
+    } else if (gr) {
+      (void)hipGraphDestroy(gr);
+    }
+  }
+  if (ok) {
+    G.key = key;
+  } else {
+    G.reset();
+    (void)hipGetLastError();
+    *use_graph = false;
+  }
+  return RVE_OK;
+}
+
+// Drives all solves of a batch from their first sweep (already begun) to the end: replays, per-solve
+// refinement as soon as a solve's run ends, graph recapture when half of it has converged.
+// started[r]: the first sweep_begin of run r launched an MINRES run (a run with no active case did not).
+template <typename T>
+static rve_status batch_iterate(std::vector<SolveRun>& runs, const std::vector<char>& started,
+                                const rve_options* opt, hipStream_t s, StreamCache* cache) {
+  const bool fp32 = opt->precision == RVE_FP32_MIXED;
+  const int chunk = ((opt->check_every + 5) / 6) * 6;
+  const int nr = (int)runs.size();
+  std::vector<int> sweeps(nr, 1);          // runs begun so far
+  std::vector<char> done(nr, 0);           // converged, or out of sweeps
+  std::vector<SolveRun*> live;
+  for (int r = 0; r < nr; ++r) {
+    done[r] = started[r] ? 0 : 1;
+    if (!done[r]) live.push_back(&runs[r]);
+  }
+  if (live.empty()) return RVE_OK;
+  std::vector<std::vector<MinresState>> hs(nr);
+  for (int r = 0; r < nr; ++r) hs[r].resize(runs[r].nc);
+  std::vector<char> pending_check(nr, 0);  // a sweep was begun without checking for active cases
+  bool use_graph = false;
+  rve_status st = capture_multi<T>(live, chunk, s, cache, &use_graph);
+  if (st != RVE_OK) return st;
+  long long guard = 0;
+  const long long guard_max = (long long)opt->max_iter * opt->max_refine / chunk + 2LL * opt->max_refine + 8;
+  while (!live.empty()) {
+    if (++guard > guard_max) break;  // every case's iteration budget is spent by now
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(cache->multi[sizeof(T) == 8 ? 1 : 0].exec, s));
+    } else {
+      st = enqueue_multi<T>(live, chunk, s, cache);
+      if (st != RVE_OK) return st;
+    }
+    HIPCHK(hipGetLastError());
+    for (int r = 0; r < nr; ++r)
+      if (!done[r]) {
+        HIPCHK(hipMemcpyAsync(hs[r].data(), runs[r].dst, sizeof(MinresState) * runs[r].nc, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(runs[r].hci.data(), runs[r].dci, sizeof(CaseInfo) * runs[r].nc, hipMemcpyDeviceToHost,
+                              s));
+      }
+    HIPCHK(hipStreamSynchronize(s));
+    prof::flush();
+    int done_in_graph = 0;
+    for (int r = 0; r < nr; ++r) {
+      if (done[r]) {
+        // still has nodes in the graph until the next capture
+        for (SolveRun* L : live) done_in_graph += L == &runs[r];
+        continue;
+      }
+      bool all = true;
+      for (int c = 0; c < runs[r].nc; ++c) all = all && hs[r][c].finish;
+      if (!all) continue;
+      if (pending_check[r]) {
+        // the sweep just replayed was begun unchecked: with no active case it ran nothing (and the solve
+        // ends here, as solve_rve's loop ends on a sweep without active cases)
+        bool any = false;
+        for (int c = 0; c < runs[r].nc; ++c) any = any || runs[r].hci[c].active;
+        pending_check[r] = 0;
+        if (!any) {
+          done[r] = 1;
+          continue;
+        }
+      }
+      st = runs[r].sweep_end();
+      if (st != RVE_OK) return st;
+      if (fp32 && sweeps[r] < opt->max_refine) {
+        st = runs[r].sweep_begin(nullptr);  // its active flags are checked after the next replay
+        if (st != RVE_OK) return st;
+        sweeps[r]++;
+        pending_check[r] = 1;
+      } else {
+        done[r] = 1;  // counted among the graph's finished solves from the next replay on
+      }
+    }
+    std::vector<SolveRun*> still;
+    for (int r = 0; r < nr; ++r)
+      if (!done[r]) still.push_back(&runs[r]);
+    if (still.empty()) break;
+    if (2 * done_in_graph >= (int)live.size() || !use_graph) {
+      if (still.size() != live.size()) {
+        live.swap(still);
+        if (use_graph) {
+          st = capture_multi<T>(live, chunk, s, cache, &use_graph);
+          if (st != RVE_OK) return st;
+        }
+      }
+    }
   }
   return RVE_OK;
 }
@@ -864,7 +1335,6 @@ void rve_default_options(rve_options* o) {
   o->inner_safety = 0.9;
   o->stress_mask = 0;
   o->macro_stress = nullptr;
-  o->alpha_mode = RVE_ALPHA_CV;
 }
 
 int32_t rve_supported_length(int32_t n) {
@@ -1185,7 +1655,6 @@ static rve_status validate_options(const rve_options* o) {
   if (!(o->inner_floor > 0 && o->inner_floor < 1) || !(o->inner_safety > 0 && o->inner_safety <= 1))
     return RVE_EINVAL;
   if (o->stress_mask < 0 || o->stress_mask > 63) return RVE_EINVAL;
-  if (o->alpha_mode != RVE_ALPHA_CV && o->alpha_mode != RVE_ALPHA_AV) return RVE_EINVAL;
   return RVE_OK;
 }
 
@@ -1296,244 +1765,45 @@ static rve_status solve_impl(const rve_grid* grid, const float* phi, const doubl
   rve_status st = rve_validate(grid, phase_stiffness, macro_strain, n_cases, opt);
   if (st != RVE_OK) return st;
   if (!phi || !strain_out || !eff_stress || !iterations || !rel_residual || !workspace) return RVE_EINVAL;
-  Plan pl;
-  if (!make_plan(grid, &pl)) return RVE_EUNSUPPORTED_SIZE;
-  const int nc = n_cases;
-  const int prec = opt->precision;
-  const Layout L = make_layout(pl, nc, prec, true);
-  if ((long long)workspace_bytes < L.total) return RVE_ENOMEM;
   hipStream_t s = (hipStream_t)hip_stream;
+  SolveRun R;
+  st = R.init(grid, phi, 0, phase_stiffness, macro_strain, opt->macro_stress, n_cases, opt, (char*)workspace,
+              workspace_bytes, s);
+  if (st != RVE_OK) return st;
   StreamCache* cache = mode == kSolveNoAlloc ? nullptr : cache_acquire(s);
   CacheLease lease(cache);
   LoopCtx ctx;
   ctx.cache = cache;
   ctx.u2_inline = mode != kSolveDefault;
   ctx.allow_graph = mode != kSolveNoAlloc;
-  ctx.alpha_av = opt->alpha_mode == RVE_ALPHA_AV ? 1 : 0;
-  char* ws = (char*)workspace;
-  const GridDims& g = pl.g;
-  const long long n6 = 6 * g.nvox;
-
-  MinresState* dst = reinterpret_cast<MinresState*>(ws + L.off_state);
-  CaseInfo* dci = reinterpret_cast<CaseInfo*>(ws + L.off_info);
-  double* part = reinterpret_cast<double*>(ws + L.off_part);
-  double* sums = reinterpret_cast<double*>(ws + L.off_sums);
-  int* flag = reinterpret_cast<int*>(ws + L.off_flag);
-  double* x64 = reinterpret_cast<double*>(ws + L.off_x64);
-  double* b64 = reinterpret_cast<double*>(ws + L.off_b64);
-  double* r64 = reinterpret_cast<double*>(ws + L.off_r64);
-  double* t64 = reinterpret_cast<double*>(ws + L.off_t64);
-  cx<double>* spec64 = reinterpret_cast<cx<double>*>(ws + L.off_spec64);
-
-  // phi validity (device pre-pass)
-  HIPCHK(hipMemsetAsync(flag, 0, 64, s));
-  hipLaunchKernelGGL(k_check_phi, dim3(256), dim3(256), 0, s, phi, g.nvox, flag);
-  int hflag[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (hflag[0]) return RVE_ENONFINITE;
-  if (hflag[1]) return RVE_EINVAL;
-
-  // tables, material, macro strains
-  rve_status r = build_tables<double>(pl, grid, ws + L.off_tab64, opt->scheme, opt->nyquist, s);
-  if (r != RVE_OK) return r;
-  Tables<double> tb64 = tables_at<double>(pl, ws + L.off_tab64);
-  tb64.stress_mask = opt->stress_mask;
-  Material<double> mat64 = make_material<double>(phase_stiffness, phase_stiffness + 36);
-  Tables<float> tb32;
-  Material<float> mat32 = make_material<float>(phase_stiffness, phase_stiffness + 36);
-  if (prec == RVE_FP32_MIXED) {
-    r = build_tables<float>(pl, grid, ws + L.off_tab32, opt->scheme, opt->nyquist, s);
-    if (r != RVE_OK) return r;
-    tb32 = tables_at<float>(pl, ws + L.off_tab32);
-    tb32.stress_mask = opt->stress_mask;
+  st = R.check_phi();
+  if (st != RVE_OK) return st;
+  st = R.setup(eps0);
+  if (st != RVE_OK) return st;
+  const bool fp32 = opt->precision == RVE_FP32_MIXED;
+  const int sweeps = fp32 ? opt->max_refine : 1;  // FP64: one MINRES run
+  for (int sweep = 0; sweep < sweeps; ++sweep) {
+    bool any = false;
+    st = R.sweep_begin(&any);
+    if (st != RVE_OK) return st;
+    if (fp32 && !any) break;
+    st = fp32 ? minres_loop<float>(R.pl, R.nc, R.B32, phi, R.mat32, R.tb32, R.spec32, R.dst, R.part, opt->max_iter,
+                                   opt->check_every, s, ctx)
+              : minres_loop<double>(R.pl, R.nc, R.B64, phi, R.mat64, R.tb64, R.spec64, R.dst, R.part, opt->max_iter,
+                                    opt->check_every, s, ctx);
+    if (st != RVE_OK) return st;
+    st = R.sweep_end();
+    if (st != RVE_OK) return st;
   }
-  // Mixed macroscopic control (eq. galop, eq. gallin): the macroscopic strain acts on the
-  // strain-controlled components only, the macroscopic stress on the stress-controlled ones
-  std::vector<double> hE(6 * nc), hS(6 * nc, 0.0);
-  for (int c = 0; c < nc; ++c)
-    for (int a = 0; a < 6; ++a) {
-      const bool stress_ctl = (opt->stress_mask >> a) & 1;
-      hE[c * 6 + a] = stress_ctl ? 0.0 : macro_strain[c * 6 + a];
-      if (stress_ctl && opt->macro_stress) hS[c * 6 + a] = opt->macro_stress[c * 6 + a];
-    }
-  // macro strains live in the partials buffer's head while b is formed
-  double* Ed = part;
-  double* Sd = sums + 8 * nc;  // 6 nc doubles of the 16 nc
-  HIPCHK(hipMemcpyAsync(Ed, hE.data(), sizeof(double) * 6 * nc, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(Sd, hS.data(), sizeof(double) * 6 * nc, hipMemcpyHostToDevice, s));
-  dim3 vg, vb;
-  vec_grid(nc, &vg, &vb);
-  // b = -A(Ebar) + Ghat(0) Sbar  (FP64 operator; a uniform Sbar transforms to xi = 0 only, where the
-  // projection keeps its stress-controlled components), and ||b||
-  hipLaunchKernelGGL(k_fill_const<double>, vg, vb, 0, s, x64, Ed, g.nvox);
-  apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, nullptr, 0, s);
-  hipLaunchKernelGGL(k_rhs, vg, vb, 0, s, b64, r64, Sd, g.nvox, part);
-  hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums, 1, 1);
-  // CaseInfo init on host then upload
-  std::vector<CaseInfo> hci(nc);
-  std::vector<double> hb(nc);
-  HIPCHK(hipMemcpyAsync(hb.data(), sums, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  for (int c = 0; c < nc; ++c) {
-    hci[c].bnorm = hb[c];
-    hci[c].rnorm = hb[c];
-    hci[c].iters = 0;
-    hci[c].status = 0;
-    hci[c].warm_rejected = 0;
-    hci[c].r0 = hb[c];
-    hci[c].active = 1;
-  }
-  // A right-hand side at the rounding level of the transforms of a constant field counts as zero:
-  // the homogeneous case, answered exactly by eps = 0.
-  {
-    double scale = 0;
-    for (int c = 0; c < nc; ++c) {
-      double cn = 0;
-      for (int i = 0; i < 36; ++i) cn = std::max(cn, std::fabs(phase_stiffness[36 + i]));
-      double en = 0, sn = 0;
-      for (int i = 0; i < 6; ++i) en = std::max(en, std::fabs(hE[c * 6 + i]));
-      for (int i = 0; i < 6; ++i) sn = std::max(sn, std::fabs(hS[c * 6 + i]));
-      scale = (cn * en + sn) * std::sqrt((double)n6);
-      if (hci[c].bnorm <= 1e-13 * scale) {
-        hci[c].bnorm = 0.0;
-        hci[c].active = 0;
-      }
-    }
-  }
-  HIPCHK(hipMemcpyAsync(dci, hci.data(), sizeof(CaseInfo) * nc, hipMemcpyHostToDevice, s));
-  // re-upload Ebar (part was overwritten by the norm partials)
-  double* Ed2 = sums;  // needs 6*nc doubles: sums holds 16*nc
-  HIPCHK(hipMemcpyAsync(Ed2, hE.data(), sizeof(double) * 6 * nc, hipMemcpyHostToDevice, s));
-
-  // projection material: C = identity independent of phi
-  Material<double> ident64;
-  memset(&ident64, 0, sizeof(ident64));
-  for (int i = 0; i < 6; ++i) ident64.C0[i * 7] = 1.0;
-  ident64.has_c0 = 1;
-  ident64.use_phi = 0;
-  // start: x64 = 0 or projected warm start; r64 = b - A x64
-  if (eps0) {
-    // x64 = Ghat eps0 (projection, C = identity)
-    const Material<double>& id = ident64;
-    if (prec == RVE_FP32_MIXED) {
-      hipLaunchKernelGGL((k_lincomb<float, double>), vg, vb, 0, s, r64, (const float*)eps0, 1.0,
-                         (const double*)nullptr, 0.0, n6, part);
-    } else {
-      hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, (const double*)eps0, 1.0,
-                         (const double*)nullptr, 0.0, n6, part);
-    }
-    apply_op<double>(pl, nc, r64, nullptr, phi, id, tb64, spec64, x64, nullptr, nullptr, nullptr, nullptr, 0, s);
-    apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, nullptr, 0, s);
-    hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
-    hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
-    hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
-                       opt->max_iter);
-    hipLaunchKernelGGL(k_warm_fallback, dim3(1024, nc), dim3(256), 0, s, x64, r64, b64, dci, n6);
-    hipLaunchKernelGGL(k_residual_update_fallback, dim3((nc + 63) / 64), dim3(64), 0, s, dci, nc);
-  } else {
-    hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, x64, n6 * nc);
-    HIPCHK(hipMemcpyAsync(r64, b64, sizeof(double) * n6 * nc, hipMemcpyDeviceToDevice, s));
-  }
-  HIPCHK(hipGetLastError());
-
-  const int check = opt->check_every;
-  if (prec == RVE_FP32_MIXED) {
-    MinresBufs<float> B;
-    for (int i = 0; i < 3; ++i) B.u[i] = reinterpret_cast<float*>(ws + L.off_u32[i]);
-    for (int i = 0; i < 2; ++i) B.d[i] = reinterpret_cast<float*>(ws + L.off_d32[i]);
-    B.x = reinterpret_cast<float*>(ws + L.off_x32);
-    cx<float>* spec32 = reinterpret_cast<cx<float>*>(ws + L.off_spec32);
-    for (int sweep = 0; sweep < opt->max_refine; ++sweep) {
-      // any case active?
-      HIPCHK(hipMemcpyAsync(hci.data(), dci, sizeof(CaseInfo) * nc, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      bool any = false;
-      for (int c = 0; c < nc; ++c) any = any || hci[c].active;
-      if (!any) break;
-      // u_1 = fp32(r64), u_0 = d = x32 = 0
-      hipLaunchKernelGGL((k_lincomb<double, float>), vg, vb, 0, s, B.u[1], r64, 1.0, (const double*)nullptr, 0.0,
-                         n6, part);
-      hipLaunchKernelGGL(k_minres_init, dim3(nc), dim3(kThreads), 0, s, dst, part, kRedBlocks, dci, opt->tol,
-                         opt->inner_safety, opt->inner_floor, opt->max_iter);
-      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B.u[0], n6 * nc);
-      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B.d[0], n6 * nc);
-      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B.d[1], n6 * nc);
-      hipLaunchKernelGGL(k_zero<float>, dim3(1024), dim3(256), 0, s, B.x, n6 * nc);
-      // rotate buffers so that u_{k-1} = u[0], u_k = u[1], p = u[2]
-      r = minres_loop<float>(pl, nc, B, phi, mat32, tb32, spec32, dst, part, opt->max_iter, check, s, ctx);
-      if (r != RVE_OK) return r;
-      hipLaunchKernelGGL(k_sweep_done, dim3((nc + 63) / 64), dim3(64), 0, s, dst, dci, nc);
-      // x64 += x32 ; r64 = b - A x64
-      hipLaunchKernelGGL(k_accum<float>, vg, vb, 0, s, x64, B.x, n6, (const int*)nullptr);
-      // The exact fluctuation is compatible and has zero mean.  FP32 rounding inside the sweep leaves
-      // incompatible components (a mean among them) that the projected residual cannot see but the
-      // average stress does: project the FP64 iterate back onto compatible fields.
-      apply_op<double>(pl, nc, x64, nullptr, phi, ident64, tb64, spec64, t64, nullptr, nullptr, nullptr, nullptr, 0, s);
-      std::swap(x64, t64);
-      apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, nullptr, 0, s);
-      hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
-      hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
-      hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
-                         opt->max_iter);
-      HIPCHK(hipGetLastError());
-    }
-  } else {
-    MinresBufs<double> B;
-    for (int i = 0; i < 3; ++i) B.u[i] = reinterpret_cast<double*>(ws + L.off_u64[i]);
-    for (int i = 0; i < 2; ++i) B.d[i] = reinterpret_cast<double*>(ws + L.off_d64[i]);
-    B.x = x64;
-    // FP64: one MINRES on A x = b from the start x64 (r64 = b - A x64)
-    hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, B.u[1], r64, 1.0, (const double*)nullptr, 0.0, n6,
-                       part);
-    hipLaunchKernelGGL(k_minres_init, dim3(nc), dim3(kThreads), 0, s, dst, part, kRedBlocks, dci, opt->tol, 1.0,
-                       1e-300, opt->max_iter);
-    hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, B.u[0], n6 * nc);
-    hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, B.d[0], n6 * nc);
-    hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, B.d[1], n6 * nc);
-    r = minres_loop<double>(pl, nc, B, phi, mat64, tb64, spec64, dst, part, opt->max_iter, check, s, ctx);
-    if (r != RVE_OK) return r;
-    hipLaunchKernelGGL(k_sweep_done, dim3((nc + 63) / 64), dim3(64), 0, s, dst, dci, nc);
-    apply_op<double>(pl, nc, x64, nullptr, phi, mat64, tb64, spec64, r64, nullptr, nullptr, nullptr, nullptr, 0, s);
-    hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, r64, -1.0, b64, 1.0, n6, part);
-    hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums + 6 * nc, 1, 0);
-    hipLaunchKernelGGL(k_residual_update, dim3((nc + 63) / 64), dim3(64), 0, s, dci, sums + 6 * nc, nc, opt->tol,
-                       opt->max_iter);
-  }
-  HIPCHK(hipGetLastError());
-
-  // post-processing: strain/stress fields, <sigma> and <eps>
-  HIPCHK(hipMemcpyAsync(Ed2, hE.data(), sizeof(double) * 6 * nc, hipMemcpyHostToDevice, s));
-  if (prec == RVE_FP32_MIXED) {
-    hipLaunchKernelGGL(k_post<float>, dim3(kRedBlocks, nc), dim3(kThreads), 0, s, x64, phi, mat64, Ed2,
-                       (float*)strain_out, (float*)stress_out, g.nvox, part);
-  } else {
-    hipLaunchKernelGGL(k_post<double>, dim3(kRedBlocks, nc), dim3(kThreads), 0, s, x64, phi, mat64, Ed2,
-                       (double*)strain_out, (double*)stress_out, g.nvox, part);
-  }
-  hipLaunchKernelGGL(k_sum_partials, dim3(6 * nc), dim3(kThreads), 0, s, part, kRedBlocks, r64, 1, 0);
-  hipLaunchKernelGGL(k_field_sums, dim3(kRedBlocks, nc), dim3(kThreads), 0, s, x64, g.nvox, part);
-  hipLaunchKernelGGL(k_sum_partials, dim3(6 * nc), dim3(kThreads), 0, s, part, kRedBlocks, r64 + 6 * nc, 1, 0);
-  std::vector<double> hs(12 * nc);
-  HIPCHK(hipMemcpyAsync(hs.data(), r64, sizeof(double) * 12 * nc, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hci.data(), dci, sizeof(CaseInfo) * nc, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(s));
-  rve_status worst_err = RVE_OK, worst_warn = RVE_OK;
-  for (int c = 0; c < nc; ++c) {
-    for (int a = 0; a < 6; ++a) eff_stress[c * 6 + a] = hs[c * 6 + a] / (double)g.nvox;
-    iterations[c] = hci[c].iters;
-    rel_residual[c] = hci[c].bnorm > 0 ? hci[c].rnorm / hci[c].bnorm : 0.0;
-    if (hci[c].status == RVE_ENONFINITE || !std::isfinite(rel_residual[c])) worst_err = RVE_ENONFINITE;
-    else if (hci[c].status == RVE_BREAKDOWN) worst_warn = RVE_BREAKDOWN;
-    else if (hci[c].bnorm > 0 && !(rel_residual[c] <= opt->tol) && worst_warn == RVE_OK) worst_warn = RVE_NOT_CONVERGED;
-  }
-  rve_status worst = worst_err != RVE_OK ? worst_err : worst_warn;
-  g_last_info.assign(nc, LastInfo{});
-  for (int c = 0; c < nc; ++c) {
-    g_last_info[c].r0_rel = hci[c].bnorm > 0 ? hci[c].r0 / hci[c].bnorm : 0.0;
-    g_last_info[c].warm_rejected = hci[c].warm_rejected;
-    for (int a = 0; a < 6; ++a) g_last_info[c].mean_strain[a] = hE[c * 6 + a] + hs[6 * nc + c * 6 + a] / (double)g.nvox;
+  std::vector<double> ms(6 * (size_t)n_cases);
+  rve_status worst = RVE_OK;
+  st = R.post(0, n_cases, strain_out, stress_out, eff_stress, iterations, rel_residual, ms.data(), &worst);
+  if (st != RVE_OK) return st;
+  g_last_info.assign(n_cases, LastInfo{});
+  for (int c = 0; c < n_cases; ++c) {
+    g_last_info[c].r0_rel = R.hci[c].bnorm > 0 ? R.hci[c].r0 / R.hci[c].bnorm : 0.0;
+    g_last_info[c].warm_rejected = R.hci[c].warm_rejected;
+    for (int a = 0; a < 6; ++a) g_last_info[c].mean_strain[a] = ms[c * 6 + a];
   }
   return worst;
 }
@@ -1622,9 +1892,11 @@ int32_t rve_cache_counts(int64_t* counts4) {
   int64_t sets = 0, streams = 0, events = 0, graphs = 0;
   for (const StreamCache* c : g_caches) {
     sets++;
-    streams += c->u2.s2 != nullptr;
-    events += (int64_t)c->u2.after_p2.size() + (int64_t)c->u2.after_u2.size();
-    graphs += (c->graph[0].exec != nullptr) + (c->graph[1].exec != nullptr);
+    streams += (c->u2.s2 != nullptr) + (int64_t)c->branch.size();
+    events += (int64_t)c->u2.after_p2.size() + (int64_t)c->u2.after_u2.size() + (int64_t)c->join.size() +
+              (c->fork != nullptr);
+    graphs += (c->graph[0].exec != nullptr) + (c->graph[1].exec != nullptr) + (c->multi[0].exec != nullptr) +
+              (c->multi[1].exec != nullptr);
   }
   if (counts4) {
     counts4[0] = sets;
@@ -1636,22 +1908,79 @@ int32_t rve_cache_counts(int64_t* counts4) {
 }
 
 // ---------------------------------------------------------------------------- heterogeneous batches
-size_t rve_batch_workspace_bytes(const rve_batch_item* items, int32_t n_items, const rve_options* opt,
-                                 int32_t n_streams) {
-  if (!items || n_items < 1 || n_streams < 1 || !opt) return 0;
-  size_t mx = 0;
+// RVEs with the same grid (lengths and cell size) and the same phase stiffness form one group; a group
+// is one multi-case solve whose load cases are the cases of all its RVEs, each case with its own copy
+// of its RVE's phase map (and warm start) in the group's workspace region.  Groups run their sweeps in
+// lockstep, and their MINRES iterations run as the parallel branches of one captured graph.
+struct BatchGroup {
+  std::vector<int> items;  // item indices
+  std::vector<int> c0;     // first case of each item within the group
+  int nc = 0;
+  long long nvox = 0;
+  bool warm = false;
+  size_t off_ws = 0, ws_bytes = 0, off_phi = 0, off_eps0 = 0;
+};
+
+static bool same_group(const rve_batch_item& a, const rve_batch_item& b) {
+  for (int p = 0; p < 3; ++p)
+    if (a.grid.n[p] != b.grid.n[p] || a.grid.L[p] != b.grid.L[p]) return false;
+  return memcmp(a.phase_stiffness, b.phase_stiffness, sizeof(double) * 72) == 0;
+}
+
+// Groups in decreasing work (voxels x cases) and their workspace carve-out; 0 total on a bad item.
+static size_t plan_batch(const rve_batch_item* items, int n_items, const rve_options* opt,
+                         std::vector<BatchGroup>* groups) {
+  groups->clear();
   for (int i = 0; i < n_items; ++i) {
-    const size_t b = rve_workspace_bytes(&items[i].grid, items[i].n_cases, opt);
-    if (b == 0) return 0;
-    mx = std::max(mx, b);
+    BatchGroup* gp = nullptr;
+    for (auto& g : *groups)
+      if (same_group(items[g.items[0]], items[i])) gp = &g;
+    if (!gp) {
+      groups->push_back(BatchGroup{});
+      gp = &groups->back();
+    }
+    gp->c0.push_back(gp->nc);
+    gp->items.push_back(i);
+    gp->nc += items[i].n_cases;
+    gp->warm = gp->warm || items[i].eps0 != nullptr;
   }
-  const size_t slot = (mx + 255) / 256 * 256;
-  return slot * (size_t)std::min(n_streams, n_items);
+  std::stable_sort(groups->begin(), groups->end(), [&](const BatchGroup& a, const BatchGroup& b) {
+    const rve_grid& ga = items[a.items[0]].grid;
+    const rve_grid& gb = items[b.items[0]].grid;
+    return (double)ga.n[0] * ga.n[1] * ga.n[2] * a.nc > (double)gb.n[0] * gb.n[1] * gb.n[2] * b.nc;
+  });
+  const size_t elem = opt->precision == RVE_FP64 ? 8 : 4;
+  size_t off = 0;
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  for (auto& g : *groups) {
+    const rve_grid& gr = items[g.items[0]].grid;
+    g.nvox = (long long)gr.n[0] * gr.n[1] * gr.n[2];
+    const size_t w = rve_workspace_bytes(&gr, g.nc, opt);
+    if (w == 0) return 0;
+    g.off_ws = off;
+    g.ws_bytes = up(w);
+    off += g.ws_bytes;
+    g.off_phi = off;
+    off += up(sizeof(float) * (size_t)g.nvox * g.nc);
+    if (g.warm) {
+      g.off_eps0 = off;
+      off += up(elem * 6 * (size_t)g.nvox * g.nc);
+    }
+  }
+  return off;
+}
+
+size_t rve_batch_workspace_bytes(const rve_batch_item* items, int32_t n_items, const rve_options* opt) {
+  if (!items || n_items < 1 || !opt) return 0;
+  for (int i = 0; i < n_items; ++i)
+    if (rve_workspace_bytes(&items[i].grid, items[i].n_cases, opt) == 0 || !items[i].phase_stiffness) return 0;
+  std::vector<BatchGroup> groups;
+  return plan_batch(items, n_items, opt, &groups);
 }
 
 rve_status solve_rve_batch(rve_batch_item* items, int32_t n_items, const rve_options* opt, void* workspace,
-                           size_t workspace_bytes, void* const* hip_streams, int32_t n_streams) {
-  if (!items || n_items < 1 || !opt || !workspace || !hip_streams || n_streams < 1) return RVE_EINVAL;
+                           size_t workspace_bytes, void* hip_stream) {
+  if (!items || n_items < 1 || !opt || !workspace) return RVE_EINVAL;
   for (int i = 0; i < n_items; ++i) {
     rve_options o = *opt;
     o.macro_stress = items[i].macro_stress;
@@ -1661,47 +1990,83 @@ rve_status solve_rve_batch(rve_batch_item* items, int32_t n_items, const rve_opt
         !items[i].rel_residual)
       return RVE_EINVAL;
   }
-  const int workers = std::min(n_streams, n_items);
-  const size_t need = rve_batch_workspace_bytes(items, n_items, opt, workers);
+  std::vector<BatchGroup> groups;
+  const size_t need = plan_batch(items, n_items, opt, &groups);
   if (need == 0) return RVE_EINVAL;
   if (workspace_bytes < need) return RVE_ENOMEM;
-  const size_t slot = need / workers;
-  // largest work first (voxels x load cases), claimed dynamically by the stream workers
-  std::vector<int> order(n_items);
-  for (int i = 0; i < n_items; ++i) order[i] = i;
-  auto work = [&](int i) {
-    return (double)items[i].grid.n[0] * items[i].grid.n[1] * items[i].grid.n[2] * items[i].n_cases;
-  };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-  std::atomic<int> next{0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return RVE_EDEVICE;
-  auto worker = [&](int w) {
-    if (hipSetDevice(dev) != hipSuccess) return;
-    char* ws = (char*)workspace + slot * w;
-    for (;;) {
-      const int k = next.fetch_add(1);
-      if (k >= n_items) break;
-      rve_batch_item& it = items[order[k]];
-      // U2 stays on the worker's stream: the RVEs already overlap each other, and a second stream per
-      // worker would double the streams sharing the process's few hardware queues (measured: the
-      // 64-RVE batch went from 2.9 to 3.7 s with side streams)
-      rve_options o = *opt;
-      o.macro_stress = it.macro_stress;
-      it.status = solve_impl(&it.grid, it.voxel_fraction_field, it.phase_stiffness, it.macro_strain, it.n_cases,
-                             &o, it.eps0, it.strain_out, it.stress_out, it.eff_stress, it.iterations,
-                             it.rel_residual, ws, slot, hip_streams[w], kSolveBatch);
+  hipStream_t s = (hipStream_t)hip_stream;
+  char* ws = (char*)workspace;
+  const size_t elem = opt->precision == RVE_FP64 ? 8 : 4;
+  const int ng = (int)groups.size();
+  // per group: stacked loads, phase maps (and warm starts) per case
+  std::vector<std::vector<double>> strains(ng), stresses(ng);
+  std::vector<SolveRun> runs(ng);
+  for (int gi = 0; gi < ng; ++gi) {
+    BatchGroup& G = groups[gi];
+    strains[gi].assign(6 * (size_t)G.nc, 0.0);
+    stresses[gi].assign(6 * (size_t)G.nc, 0.0);
+    bool any_stress = false;
+    float* phis = reinterpret_cast<float*>(ws + G.off_phi);
+    for (size_t k = 0; k < G.items.size(); ++k) {
+      const rve_batch_item& it = items[G.items[k]];
+      for (int c = 0; c < it.n_cases; ++c) {
+        const int cc = G.c0[k] + c;
+        for (int a = 0; a < 6; ++a) {
+          strains[gi][cc * 6 + a] = it.macro_strain[c * 6 + a];
+          if (it.macro_stress) stresses[gi][cc * 6 + a] = it.macro_stress[c * 6 + a];
+        }
+        any_stress = any_stress || it.macro_stress != nullptr;
+        HIPCHK(hipMemcpyAsync(phis + (size_t)cc * G.nvox, it.voxel_fraction_field, sizeof(float) * G.nvox,
+                              hipMemcpyDeviceToDevice, s));
+      }
+      if (G.warm) {
+        char* e0 = ws + G.off_eps0 + elem * 6 * (size_t)G.nvox * G.c0[k];
+        const size_t bytes = elem * 6 * (size_t)G.nvox * it.n_cases;
+        if (it.eps0)
+          HIPCHK(hipMemcpyAsync(e0, it.eps0, bytes, hipMemcpyDeviceToDevice, s));
+        else
+          HIPCHK(hipMemsetAsync(e0, 0, bytes, s));  // zero start for the items that bring none
+      }
     }
-  };
-  std::vector<std::thread> th;
-  for (int w = 1; w < workers; ++w) th.emplace_back(worker, w);
-  worker(0);
-  for (auto& t : th) t.join();
+    const rve_batch_item& first = items[G.items[0]];
+    rve_status st = runs[gi].init(&first.grid, phis, G.nvox, first.phase_stiffness, strains[gi].data(),
+                                  any_stress ? stresses[gi].data() : nullptr, G.nc, opt, ws + G.off_ws, G.ws_bytes, s);
+    if (st != RVE_OK) return st;
+  }
+  for (int gi = 0; gi < ng; ++gi) {
+    rve_status st = runs[gi].check_phi();
+    if (st != RVE_OK) return st;
+    st = runs[gi].setup(groups[gi].warm ? (const void*)(ws + groups[gi].off_eps0) : nullptr);
+    if (st != RVE_OK) return st;
+  }
+  StreamCache* cache = cache_acquire(s);
+  CacheLease lease(cache);
+  const bool fp32 = opt->precision == RVE_FP32_MIXED;
+  std::vector<char> started(ng, 0);
+  for (int gi = 0; gi < ng; ++gi) {
+    bool any = false;
+    rve_status st = runs[gi].sweep_begin(&any);
+    if (st != RVE_OK) return st;
+    started[gi] = (any || !fp32) ? 1 : 0;  // FP64 always starts its one run (inactive cases finish at once)
+  }
+  {
+    rve_status st = fp32 ? batch_iterate<float>(runs, started, opt, s, cache)
+                         : batch_iterate<double>(runs, started, opt, s, cache);
+    if (st != RVE_OK) return st;
+  }
   rve_status worst_err = RVE_OK, worst_warn = RVE_OK;
-  for (int i = 0; i < n_items; ++i) {
-    const rve_status s = (rve_status)items[i].status;
-    if (s < 0 && worst_err == RVE_OK) worst_err = s;
-    if (s > 0 && worst_warn == RVE_OK) worst_warn = s;
+  for (int gi = 0; gi < ng; ++gi) {
+    BatchGroup& G = groups[gi];
+    for (size_t k = 0; k < G.items.size(); ++k) {
+      rve_batch_item& it = items[G.items[k]];
+      rve_status w = RVE_OK;
+      rve_status st = runs[gi].post(G.c0[k], it.n_cases, it.strain_out, it.stress_out, it.eff_stress, it.iterations,
+                                    it.rel_residual, it.mean_strain, &w);
+      if (st != RVE_OK) return st;
+      it.status = w;
+      if (w < 0 && worst_err == RVE_OK) worst_err = w;
+      if (w > 0 && worst_warn == RVE_OK) worst_warn = w;
+    }
   }
   return worst_err != RVE_OK ? worst_err : worst_warn;
 }

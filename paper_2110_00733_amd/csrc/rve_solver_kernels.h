@@ -229,29 +229,6 @@ __global__ void k_minres_givens(MinresState* st, const double* partials, int np,
   }
 }
 
-// Lanczos three-term update when alpha comes from <v_k, A v_k> (P5 stored p = A v_k in u):
-// u_{k+1} = p - cu_v u_k - cu_vp u_{k-1} in place, per-block ||u_{k+1}||^2 partials.  Grid (blocks, nc).
-template <typename T>
-__global__ __launch_bounds__(256) void k_lanczos(T* u, const T* uk, const T* ukm1, const MinresState* st,
-                                                 long long n6, double* partials) {
-  __shared__ double red[16];
-  const int cs = blockIdx.y;
-  const MinresState& S = st[cs];
-  double acc = 0.0;
-  if (!S.finish) {
-    const T cv = (T)S.cu_v, cvp = (T)S.cu_vp;
-    const long long off = (long long)cs * n6;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n6;
-         i += (long long)gridDim.x * blockDim.x) {
-      const T v = u[off + i] - cv * uk[off + i] - cvp * ukm1[off + i];
-      u[off + i] = v;
-      acc += (double)v * (double)v;
-    }
-  }
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[(long long)cs * gridDim.x + blockIdx.x] = s;
-}
-
 // U2: d_k = cd_u u_k + cd_d1 d_{k-1} + cd_d2 d_{k-2} (written over d_{k-2}); the solution update
 // the slot's xmode schedules (x += cx d_k plus the terms deferred from the two previous iterations).
 // One 16-byte vector per thread over a grid that covers the field once (a grid-stride loop over a
@@ -312,13 +289,25 @@ __global__ void k_sweep_done(const MinresState* st, CaseInfo* ci, int nc) {
 }
 
 // After a true-residual evaluation: rnorm from the summed partial; decide whether another sweep runs.
+// A case that had already stopped keeps its residual and stays stopped (its iterate did not change, and
+// the recomputed residual could only differ by rounding), so every case's result is independent of how
+// many sweeps the other cases of the solve need.
 __global__ void k_residual_update(CaseInfo* ci, const double* sums, int nc, double tol, int max_iter) {
   const int cs = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cs >= nc) return;
+  if (cs >= nc || !ci[cs].active) return;
   ci[cs].rnorm = sqrt(sums[cs]);
   const bool conv = ci[cs].bnorm == 0.0 || ci[cs].rnorm <= tol * ci[cs].bnorm;
   const bool bad = ci[cs].status == RVE_ENONFINITE || ci[cs].status == RVE_BREAKDOWN;
   ci[cs].active = (!conv && !bad && ci[cs].iters < max_iter) ? 1 : 0;
+}
+
+// keep = x for the cases that did not run the sweep (their re-projection is not used).  Grid (blocks, nc).
+__global__ void k_keep_inactive(double* keep, const double* x, const CaseInfo* ci, long long n6) {
+  const int cs = blockIdx.y;
+  if (ci[cs].active) return;
+  const long long off = (long long)cs * n6;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n6; i += (long long)gridDim.x * blockDim.x)
+    keep[off + i] = x[off + i];
 }
 
 // A warm start that does not reduce the residual below ||b|| is dropped: x = 0, r = b (the zero
@@ -357,6 +346,7 @@ __global__ void k_post(const double* x64, const float* phi, Material<double> mat
   __shared__ double red[16];
   const int cs = blockIdx.y;
   const long long off = (long long)cs * 6 * nvox;
+  const float* phic = phi + (long long)cs * mat.phi_stride;
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (long long)gridDim.x * blockDim.x) {
     double e[6];
@@ -366,7 +356,7 @@ __global__ void k_post(const double* x64, const float* phi, Material<double> mat
       if (strain_out) strain_out[off + c * nvox + v] = (To)f;
       e[c] = E[cs * 6 + c] + f;
     }
-    const double ph = phi[v];
+    const double ph = phic[v];
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
       double s = 0, s0 = 0;
