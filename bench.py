@@ -84,9 +84,10 @@ def method_bytes_per_voxel_apply(n2, elem):
     return (6 * elem + 4 + spec) + (spec + 6 * elem)
 
 
-def algorithmic_bytes(kind, n, nc, elem):
+def algorithmic_bytes(kind, n, nc, elem, plain_apply=False):
     """Bytes one launch of a pass must move (each of its operands read or written once), FP32/FP64
-    fields.  Summed over the passes of one iteration this is the implementation's operand traffic
+    fields.  plain_apply: the operator apply of a residual check, whose P5 writes A x without the
+    Lanczos combination (no u_k, u_k-1 reads).  Summed over the passes of one iteration this is the implementation's operand traffic
     (406 B per voxel-iteration in FP32 at 256^3), about 1.3 times the method's own count above: the
     five-pass transform writes and reads the spectrum between passes."""
     n0, n1, n2 = n
@@ -98,7 +99,7 @@ def algorithmic_bytes(kind, n, nc, elem):
         "P2_fft_axis1": 2 * spec,
         "P3_fft_axis0_projection": 2 * spec,
         "P4_ifft_axis1": 2 * spec,
-        "P5_ifft_axis2_lanczos": spec + 3 * field,        # spectrum, u_k, u_k-1 -> u_k+1
+        "P5_ifft_axis2_lanczos": spec + (1 if plain_apply else 3) * field,  # spectrum, u_k, u_k-1 -> u_k+1
         # u_k, d_k-1, d_k-2 -> d_k every iteration; x read and written every third one (4 2/3 fields on average)
         "U2_direction_update": 14 * field // 3,
     }
@@ -269,7 +270,7 @@ def main():
         if work <= 0:
             continue
         avg = ms / work
-        ab = algorithmic_bytes(k[:-4] if is64 else k, n, nc, 8 if is64 else 4)
+        ab = algorithmic_bytes(k[:-4] if is64 else k, n, nc, 8 if is64 else 4, plain_apply=not own)
         kernels[k] = {"total_ms": ms, "launches": cnt, "working_launches": round(work, 1), "avg_us": 1e3 * avg,
                       "alg_bytes": ab, "gbs": (ab / (avg * 1e-3) / 1e9) if ab else None}
     # U2 runs on a second stream beside the next iteration's P3 in the timed solve, so its time there

@@ -77,6 +77,24 @@ def uniforms(seed: int, count: int) -> np.ndarray:
     return out
 
 
+def octet_struts(radius: float) -> np.ndarray:
+    """Strut list of the octet truss (input description of the lattice): 24 rows (a[3], b[3], r) with
+    endpoints in fractions of the cubic cell: the FCC basis points joined to their nearest neighbours
+    along the six face diagonals, as in the section "Lattice geometry and simulation parameters"."""
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]], dtype=np.float64)
+    dirs = np.array([[0.5, 0.5, 0], [0.5, -0.5, 0], [0.5, 0, 0.5], [0.5, 0, -0.5], [0, 0.5, 0.5], [0, 0.5, -0.5]],
+                    dtype=np.float64)
+    out = np.zeros((24, 7))
+    k = 0
+    for b in basis:
+        for d in dirs:
+            out[k, 0:3] = b
+            out[k, 3:6] = b + d
+            out[k, 6] = radius
+            k += 1
+    return out
+
+
 def octet_radius(n, rho: float, sub: int = 4) -> float:
     """Strut radius (unit cell = 1) whose S^3-subsampled phase map has mean exactly round(rho*N*S^3)/(N*S^3)."""
     _, c = _n3(n)

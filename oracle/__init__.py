@@ -6,7 +6,8 @@ FP64, OpenMP over FFT lines); this module converts between the Mandel vectors us
 interface and the Cartesian tensor components used inside the oracle.
 
 Paper sections followed: "Galerkin-FFT with discrete differences and mixed loading control"
-(eqs. freq, galop, gallin, linearOp, galres, freqrot) and "Voigt approaches" (C = phi C_m).
+(eqs. freq, galop, gallin, linearOp, galres, freqrot) and "Voigt approaches" (C = phi C_m).  The
+surface-smoothening phase maps (VFG, VA, phase field, combined) are in ``oracle.geometry``.
 Every function is pinned by CPU tests against closed forms, brute force or invariants.
 """
 from __future__ import annotations
@@ -18,7 +19,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "galerkin_oracle.c")
+_SRCS = [os.path.join(_HERE, "galerkin_oracle.c"), os.path.join(_HERE, "geometry_oracle.c")]
 _SO = os.path.join(_HERE, "libgalerkin_oracle.so")
 _lib = None
 
@@ -31,7 +32,7 @@ _SHEAR_SCALE = np.array([1.0, 1.0, 1.0, np.sqrt(2.0), np.sqrt(2.0), np.sqrt(2.0)
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
-        subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-o", tmp, _SRC, "-lm"],
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-o", tmp, *_SRCS, "-lm"],
                        check=True)
         os.replace(tmp, _SO)
     return _SO
@@ -57,6 +58,8 @@ def _load():
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_time_minres.argtypes = [ip, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int]
         lib.or_time_minres.restype = ctypes.c_double
+        lib.og_distance_map.argtypes = [ip, dp, ctypes.c_int, dp, ctypes.c_int, dp]
+        lib.og_distance_map.restype = None
         _lib = lib
     return _lib
 
