@@ -372,6 +372,7 @@ static void note_hip_error(hipError_t e, const char* expr, int line) {
   snprintf(g_last_error, sizeof(g_last_error), "%s (%d) in '%s' at rve_solver.hip:%d", hipGetErrorString(e), (int)e,
            expr, line);
 }
+void set_last_error(const char* text) { snprintf(g_last_error, sizeof(g_last_error), "%s", text); }
 #define HIPCHK(x)                          \
   do {                                     \
     hipError_t e_ = (x);                   \

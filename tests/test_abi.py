@@ -36,8 +36,8 @@ def test_library_exports_every_declared_symbol():
     assert "solve_rve" in names and "rve_apply" in names
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    from paper_2110_00733_amd import nn
-    assert sorted(rve.ABI_SYMBOLS + nn.NN_ABI_SYMBOLS) == names
+    from paper_2110_00733_amd import geometry, nn
+    assert sorted(rve.ABI_SYMBOLS + nn.NN_ABI_SYMBOLS + geometry.GEOMETRY_ABI_SYMBOLS) == names
 
 
 def _smooth5(n):
