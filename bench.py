@@ -60,6 +60,11 @@ def workload(name):
                "seeds": "1000+i", "load": "6 unit Mandel strains per RVE", "load_cases": 6, "tol": 1e-6,
                "precision": "fp32-mixed", "voxels_total": int(sum(np.prod(nn) for nn, _ in rv))}
         return [tuple(nn) for nn, _ in rv], phis, np.eye(6), cfg
+    elif name == "density_study":
+        cfg = {"workload": "density_study", "rho_target": 0.1, "timed": "phase-field smoothening (PFS) of the "
+               "octet at 108^3 coarse voxels on its 540^3 fine grid (ratio 5), FP64",
+               "grid": [108, 108, 108], "ratio": 5, "fine": [540, 540, 540], "precision": "fp64"}
+        return (108, 108, 108), None, None, cfg
     else:
         raise SystemExit(f"unknown workload {name}")
     return n, phi, E, cfg
@@ -194,6 +199,8 @@ def main():
     C1 = li.isotropic_mandel(1.0, 0.3)
     if cfg["workload"] == "octet_batch64":
         return bench_batch(args, n, phi, E, cfg, C1)
+    if cfg["workload"] == "density_study":
+        return bench_density(args, cfg)
     log(f"workload {cfg['workload']} built in {time.time() - t0:.1f}s, rho={cfg['rho_actual']:.5f}")
     prec = rve.FP64 if cfg["precision"] == "fp64" else rve.FP32_MIXED
     d = torch.as_tensor(phi, device="cuda:0")
@@ -340,6 +347,75 @@ def main():
             "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64" if prec == rve.FP64 else "f32", "data": "synthetic", "config": cfg,
             "roofline": roof, "cpu_baseline": cpu, "learned_vs_plain": learned, "kernels": kernels}
+    print(json.dumps(line), flush=True)
+
+
+def bench_density(args, cfg):
+    """Surface-smoothening study (densities of PV / VFG / VA / PFS / CS over seven grids, untimed),
+    then the timed phase-field pipeline at one density-study size: fine voxels per second, per-kernel
+    times from the library's event timing, the roofline of the longest kernel and the oracle on a
+    432^3 fine grid as CPU baseline."""
+    import torch
+    import paper_2110_00733_amd as rve
+    from paper_2110_00733_amd import density_study as ds, geometry as geo
+    import lattice_inputs as li
+    t0 = time.time()
+    study = ds.run(cfg["rho_target"], log=log)
+    log(f"density study in {time.time() - t0:.1f}s, radius {study['radius']:.6f}")
+    S = li.octet_struts(study["radius"])
+    n, ratio = tuple(cfg["grid"]), cfg["ratio"]
+    m = [v * ratio for v in n]
+    ws = rve.Workspace()
+    for _ in range(max(args.warmup, 1)):
+        geo.phase_field(n, S, ratio, workspace=ws)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        geo.phase_field(n, S, ratio, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - ts) / args.steps
+    fine = int(np.prod(m))
+    rve.profile_reset()
+    rve.profile_enable(True)
+    for _ in range(max(args.profile_steps, 1)):
+        geo.phase_field(n, S, ratio, workspace=ws)
+    torch.cuda.synchronize()
+    rve.profile_enable(False)
+    prof = {k: v for k, v in rve.profile_read().items() if k.startswith("G") and v[1] > 0}
+    spec = m[0] * m[1] * (m[2] // 2 + 1) * 16
+    coarse = int(np.prod(n)) * 16  # phi and the value before the threshold, FP64
+    alg = {"G1_source_fft_axis2": spec, "G2_fft_axis1": 2 * spec, "G3_fft_axis0_helmholtz": 2 * spec,
+           "G4_ifft_axis1": 2 * spec, "G5_ifft_axis2_coarsen": spec + coarse}
+    kernels = {}
+    for k, (ms, cnt) in prof.items():
+        avg = ms / cnt
+        kernels[k] = {"avg_us": round(1e3 * avg, 2), "launches": cnt, "alg_bytes": alg[k],
+                      "gbs": round(alg[k] / (avg * 1e-3) / 1e9, 1)}
+    log(json.dumps(kernels))
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
+    kd = kernels[dom]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "avg_us": kd["avg_us"],
+            "alg_bytes_per_launch": kd["alg_bytes"],
+            "pipeline_frac": round(sum(alg.values()) / dt / 1e9 / HBM_PEAK_GBS, 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import geometry as og
+        import oracle
+        tc = time.time()
+        og.phase_field(54, S, 8)
+        secs = time.time() - tc
+        cpu = {"value": 432 ** 3 / secs, "unit": "fine voxels/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"one oracle phase-field smoothening of the same octet at 54^3 coarse voxels on a 432^3 "
+                         f"fine grid (ratio 8; C distance loops on all cores, numpy FFTs), {secs:.1f} s"}
+        log(f"cpu baseline {cpu['value']:.3e} fine voxels/s")
+    cfg.update({"radius": study["radius"], "study": study["rows"], "study_seconds": study["seconds"],
+                "ms_per_call": round(1e3 * dt, 3), "parallelism": "single-gpu"})
+    line = {"metric": "phase-field smoothening fine voxels/s (density study)", "value": fine / dt,
+            "unit": "fine voxels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic", "config": cfg, "roofline": roof, "cpu_baseline": cpu,
+            "kernels": kernels}
     print(json.dumps(line), flush=True)
 
 

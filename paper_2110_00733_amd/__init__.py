@@ -138,9 +138,10 @@ def profile_reset() -> None:
 def profile_read() -> dict:
     """{kernel kind: (total ms, launches)} accumulated since the last reset."""
     lib = load_library()
-    ms = np.zeros(16)
-    cnt = np.zeros(16, dtype=np.int64)
-    k = lib.rve_profile_read(_dp(ms), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 16)
+    kinds = int(lib.rve_profile_read(None, None, 0))
+    ms = np.zeros(kinds)
+    cnt = np.zeros(kinds, dtype=np.int64)
+    k = lib.rve_profile_read(_dp(ms), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), kinds)
     return {lib.rve_profile_kind_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}
 
 

@@ -31,6 +31,9 @@
 
 namespace rve {
 void set_last_error(const char* text);
+void geo_prof_begin(int g, hipStream_t s);
+void geo_prof_end(hipStream_t s);
+void geo_prof_flush();
 }
 
 namespace rvg {
@@ -232,16 +235,63 @@ __global__ __launch_bounds__(kThreads) void k_source_r2c(const rve_strut* __rest
   extern __shared__ unsigned char smem_raw[];
   StrutPrep* sp = reinterpret_cast<StrutPrep*>(smem_raw);
   C* buf = reinterpret_cast<C*>(smem_raw + (source ? 0 : sizeof(StrutPrep) * ns));
+  __shared__ int cand[RVE_GEOMETRY_MAX_STRUTS];
+  __shared__ int wave_cnt[kThreads / 64];
   if (!source) load_struts(struts, ns, cell.L, sp);
   __syncthreads();
   const long long rows = (long long)f.m0 * f.m1;
   const long long row0 = (long long)blockIdx.x * 2 * TP;
   const int N = f.m2, K = f.K;
+  int ncand = 0;
+  if (!source) {
+    // Candidate struts of this block's rows.  Along a row only x_2 varies and the nearest-image
+    // offsets dx_0, dx_1 to a strut midpoint are fixed, so the distance of every point of the row to
+    // the strut axis is at least the in-plane distance from (dx_0, dx_1) to the axis projected onto
+    // the (x_0, x_1) plane; a strut whose bound exceeds its radius (with a margin far above rounding)
+    // contains no point of the row and cannot change an inside/outside decision.
+    bool keep = false;
+    const int k = threadIdx.x;
+    if (k < ns) {
+#pragma clang fp contract(off)
+      const StrutPrep& q = sp[k];
+      const double h0 = q.half[0], h1 = q.half[1];
+      const double hh2 = h0 * h0 + h1 * h1;
+      const double margin = 1e-9 * (cell.L[0] + cell.L[1] + cell.L[2]);
+      for (int j = 0; j < 2 * TP && !keep; ++j) {
+        const long long row = row0 + j;
+        if (row >= rows) break;
+        const int i0 = (int)(row / f.m1), i1 = (int)(row % f.m1);
+        double d0 = ((double)i0 + 0.5) * cell.h[0] - q.mid[0];
+        double d1 = ((double)i1 + 0.5) * cell.h[1] - q.mid[1];
+        d0 -= cell.L[0] * floor(d0 / cell.L[0] + 0.5);
+        d1 -= cell.L[1] * floor(d1 / cell.L[1] + 0.5);
+        double t = hh2 > 0.0 ? (d0 * h0 + d1 * h1) / hh2 : 0.0;
+        t = t < -1.0 ? -1.0 : (t > 1.0 ? 1.0 : t);
+        const double e0 = d0 - t * h0, e1 = d1 - t * h1;
+        if (sqrt(e0 * e0 + e1 * e1) - q.r <= margin) keep = true;
+      }
+    }
+    const unsigned long long bal = __ballot(keep);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) wave_cnt[wv] = __popcll(bal);
+    __syncthreads();
+    int off = 0;
+    for (int u = 0; u < kThreads / 64; ++u) {
+      if (u < wv) off += wave_cnt[u];
+      ncand += wave_cnt[u];
+    }
+    if (keep) cand[off + __popcll(bal & ((1ull << lane) - 1ull))] = k;
+    __syncthreads();
+  }
   auto omega = [&](long long row, int e) -> double {
     const int i0 = (int)(row / f.m1), i1 = (int)(row % f.m1);
     if (source) return source[((long long)(i0 / f.ratio) * f.n1 + i1 / f.ratio) * f.n2 + e / f.ratio];
     const double x[3] = {((double)i0 + 0.5) * cell.h[0], ((double)i1 + 0.5) * cell.h[1], ((double)e + 0.5) * cell.h[2]};
-    return inside(sp, ns, cell.L, x) ? 1.0 : 0.0;
+    for (int c = 0; c < ncand; ++c) {
+      const StrutPrep& q = sp[cand[c]];
+      if (axis_distance(q, cell.L, x) - q.r <= 0.0) return 1.0;
+    }
+    return 0.0;
   };
   for (int idx = threadIdx.x; idx < TP * N; idx += blockDim.x) {
     const int w = idx / N, e = idx - w * N;
@@ -504,10 +554,13 @@ rve_status rve_phase_map(const int32_t n[3], const double L[3], const rve_strut*
   const long long nv = (long long)n[0] * n[1] * n[2];
   const int blocks = (int)std::min<long long>((nv + kThreads - 1) / kThreads, 1LL << 20);
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  rve::geo_prof_begin(5, s);
   hipLaunchKernelGGL(k_phase_map, dim3(blocks), dim3(kThreads), 0, s, struts, n_struts, cell, n[0], n[1], n[2], kind,
                      sub, ell, phi, phi_f32);
+  rve::geo_prof_end(s);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_phase_map launch");
+  rve::geo_prof_flush();
   return RVE_OK;
 }
 
@@ -560,8 +613,10 @@ rve_status rve_phase_field(const int32_t n[3], const double L[3], const rve_stru
   int TP1 = std::max(1, std::min(kRowTile / f.m2, (int)std::min<long long>((rows + 1) / 2, 64)));
   const long long g1 = (rows + 2LL * TP1 - 1) / (2LL * TP1);
   const size_t lds1 = (size_t)ns * sizeof(StrutPrep) + (size_t)TP1 * f.m2 * sizeof(C);
+  rve::geo_prof_begin(0, s);
   hipLaunchKernelGGL(k_source_r2c, dim3((unsigned)g1), dim3(kThreads), lds1, s, struts, ns, cell, source, f, lay.P[2],
                      tw[2], rev[2], TP1, spec);
+  rve::geo_prof_end(s);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_source_r2c launch");
 
   // G2: axis 1 forward
@@ -572,30 +627,39 @@ rve_status rve_phase_field(const int32_t n[3], const double L[3], const rve_stru
   hm.c = ell * ell / eps;
   hm.scale = 1.0 / ((double)f.m0 * f.m1 * f.m2);
   for (int p = 0; p < 3; ++p) hm.two_pi_over_L[p] = 2.0 * M_PI / L[p];
+  rve::geo_prof_begin(1, s);
   hipLaunchKernelGGL((k_axis_c2c<-1, false>), grid_a1, dim3(kThreads), lds_a1, s, spec, f, 1, lay.P[1], tw[1], rev[1],
                      TWa1, hm);
+  rve::geo_prof_end(s);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_axis_c2c axis 1 launch");
 
   // G3: axis 0 forward, Helmholtz multiplier, inverse
   const long long plane = (long long)f.m1 * f.K;
   const int TWa0 = std::max(1, std::min(kStridedTile / f.m0, (int)std::min<long long>(plane, 64)));
   const size_t lds_a0 = (size_t)TWa0 * f.m0 * sizeof(C);
+  rve::geo_prof_begin(2, s);
   hipLaunchKernelGGL((k_axis_c2c<-1, true>), dim3((unsigned)((plane + TWa0 - 1) / TWa0)), dim3(kThreads), lds_a0, s,
                      spec, f, 0, lay.P[0], tw[0], rev[0], TWa0, hm);
+  rve::geo_prof_end(s);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_axis_c2c axis 0 launch");
 
   // G4: axis 1 inverse
+  rve::geo_prof_begin(3, s);
   hipLaunchKernelGGL((k_axis_c2c<1, false>), grid_a1, dim3(kThreads), lds_a1, s, spec, f, 1, lay.P[1], tw[1], rev[1],
                      TWa1, hm);
+  rve::geo_prof_end(s);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_axis_c2c axis 1 inverse launch");
 
   // G5: inverse along axis 2 over the ratio^2 fine rows of each coarse row, averaged and thresholded
   const int npairs = (ratio * ratio + 1) / 2;
   const int TP5 = std::max(1, std::min(kRowTile / f.m2, npairs));
   const size_t lds5 = (size_t)TP5 * f.m2 * sizeof(C);
+  rve::geo_prof_begin(4, s);
   hipLaunchKernelGGL(k_c2r_coarsen, dim3(f.n1, f.n0), dim3(kThreads), lds5, s, spec, f, lay.P[2], tw[2], rev[2], TP5,
                      threshold, phi, phi_f32, phi_raw);
+  rve::geo_prof_end(s);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_c2r_coarsen launch");
+  rve::geo_prof_flush();
   return RVE_OK;
 }
 

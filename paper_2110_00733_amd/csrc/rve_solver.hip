@@ -73,14 +73,17 @@ static void ensure_registry() {
 // Events come from a pool created on first enable; pairs are read back at the host's chunk syncs.
 namespace prof {
 enum Kind { P1 = 0, P2, P3, P4, P5, S1, S2, U2, NKIND };
-// kinds 0..NKIND-1 time passes on FP32 fields, NKIND..2 NKIND-1 the same passes on FP64 fields
-constexpr int NSLOT = 2 * NKIND;
+// kinds 0..NKIND-1 time passes on FP32 fields, NKIND..2 NKIND-1 the same passes on FP64 fields,
+// then the phase-map kernels (FP64 only)
+constexpr int NGEO = 6;
+constexpr int NSLOT = 2 * NKIND + NGEO;
 static const char* kNames[NSLOT] = {
     "P1_stiffness_fft_axis2_alpha",     "P2_fft_axis1",     "P3_fft_axis0_projection",
     "P4_ifft_axis1",                    "P5_ifft_axis2_lanczos", "S1_alpha", "S2_givens", "U2_direction_update",
     "P1_stiffness_fft_axis2_alpha_f64", "P2_fft_axis1_f64", "P3_fft_axis0_projection_f64",
     "P4_ifft_axis1_f64",                "P5_ifft_axis2_lanczos_f64", "S1_alpha_f64", "S2_givens_f64",
-    "U2_direction_update_f64"};
+    "U2_direction_update_f64",          "G1_source_fft_axis2", "G2_fft_axis1", "G3_fft_axis0_helmholtz",
+    "G4_ifft_axis1",                    "G5_ifft_axis2_coarsen", "M_phase_map"};
 static std::atomic<bool> on{false};
 static std::vector<hipEvent_t> pool;
 static std::vector<std::pair<int, int>> pending;
@@ -89,10 +92,14 @@ static double ms[NSLOT];
 static long long cnt[NSLOT];
 static long long dropped = 0;
 static std::mutex mu;
+static inline void begin_slot(int kind, hipStream_t s);
 template <typename T>
 static inline void begin(int kind, hipStream_t s) {
   if (!on) return;
-  if (sizeof(T) == 8) kind += NKIND;
+  begin_slot(sizeof(T) == 8 ? kind + NKIND : kind, s);
+}
+static inline void begin_slot(int kind, hipStream_t s) {
+  if (!on) return;
   std::lock_guard<std::mutex> lk(mu);
   if (next + 2 > pool.size()) {
     dropped++;
@@ -127,6 +134,11 @@ static void flush() {
   next = 0;
 }
 }  // namespace prof
+
+// timing hooks of the phase-map kernels (kinds G1..G5, M in launch order)
+void geo_prof_begin(int g, hipStream_t s) { prof::begin_slot(2 * prof::NKIND + g, s); }
+void geo_prof_end(hipStream_t s) { prof::end(s); }
+void geo_prof_flush() { prof::flush(); }
 
 }  // namespace rve
 

@@ -159,3 +159,37 @@ def test_density_study_size_vs_oracle():
     phi, raw = geo.phase_field(n, S, ratio)
     o_phi, o_raw = og.phase_field(n, S, ratio)
     _check_thresholded(phi.cpu().numpy(), raw.cpu().numpy(), o_phi, o_raw, 0.05)
+
+
+def test_profiler_times_each_phase_field_pass():
+    """With the library's event timing on, one phase-field call records one launch of each of its five
+    passes and a phase map one launch of its kernel; nothing else is counted."""
+    geo = _geo()
+    import paper_2110_00733_amd as rve
+    S = li.octet_struts(0.06)
+    rve.profile_reset()
+    rve.profile_enable(True)
+    try:
+        geo.phase_field((12, 12, 12), S, 4)
+        geo.phase_map((12, 12, 12), S, geo.VA)
+    finally:
+        rve.profile_enable(False)
+    prof = rve.profile_read()
+    for k in ("G1_source_fft_axis2", "G2_fft_axis1", "G3_fft_axis0_helmholtz", "G4_ifft_axis1",
+              "G5_ifft_axis2_coarsen", "M_phase_map"):
+        assert prof[k][1] == 1 and prof[k][0] > 0, k
+    assert all(v == (0.0, 0) for k, v in prof.items() if k[0] not in "GM")
+
+
+def test_density_study_keeps_the_paper_relations():
+    """Section "Analysis of the surface smoothening approaches": before the threshold the phase field
+    keeps the density of its source (PFS that of VFG with the same fine grid, CS that of VA); the
+    threshold only removes material."""
+    _geo()
+    from paper_2110_00733_amd import density_study as ds
+    out = ds.run(0.1, grids=((24, 4), (36, 3)), radius=0.0466, log=lambda *a: None)
+    assert out["radius"] == 0.0466 and len(out["rows"]) == 2
+    for row in out["rows"]:
+        assert abs(row["PFS_before_threshold"] - row["VFG"]) < 1e-13
+        assert abs(row["CS_before_threshold"] - row["VA"]) < 1e-13
+        assert row["PFS"] <= row["PFS_before_threshold"] + 1e-15 and row["CS"] <= row["CS_before_threshold"] + 1e-15

@@ -820,7 +820,8 @@ def test_profiler_separates_precisions_and_counts_iterations():
         rve.profile_enable(False)
     prof = rve.profile_read()
     assert out["status"] == 0
-    assert len(prof) == 16
+    assert len(prof) == 22  # 8 pass kinds x 2 precisions + the 6 phase-map kernels
+    assert all(prof[k] == (0.0, 0) for k in prof if k[0] in "GM")
     its = int(out["iterations"][0])
     for k in ("P1_stiffness_fft_axis2_alpha", "P2_fft_axis1", "P3_fft_axis0_projection", "P4_ifft_axis1",
               "P5_ifft_axis2_lanczos", "U2_direction_update"):
