@@ -58,6 +58,9 @@ def _load():
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_time_minres.argtypes = [ip, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int]
         lib.or_time_minres.restype = ctypes.c_double
+        lib.or_apply_field.argtypes = [ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        lib.or_minres_field.argtypes = [ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double,
+                                        ctypes.c_int, dp, dp]
         lib.og_distance_map.argtypes = [ip, dp, ctypes.c_int, dp, ctypes.c_int, dp]
         lib.og_distance_map.restype = None
         _lib = lib

@@ -276,6 +276,7 @@ typedef struct {
   or_grid g;
   const double *phi; /* [N] */
   double C1[3][3][3][3], C0[3][3][3][3];
+  const double *Cfield; /* NULL, or a Mandel 6x6 stiffness per voxel [N][36] (replaces phi, C1, C0) */
   long N;
   cplx *work; /* [6][N] */
 } or_problem;
@@ -292,9 +293,26 @@ static double frob_dot(const double *x, const double *y, long N) {
   return acc;
 }
 
-/* sigma = C(x) : eps at every voxel, C(x) = phi C1 + (1 - phi) C0 (Voigt rule) */
+/* sigma = C(x) : eps at every voxel, C(x) = phi C1 + (1 - phi) C0 (Voigt rule), or the voxel's own
+ * Mandel stiffness (the tangent of eq. Slin) when P->Cfield is set */
 static void stiffness(const or_problem *P, const double *eps, double *sig_re_out, cplx *sig_c_out) {
   long N = P->N;
+  if (P->Cfield) {
+#pragma omp parallel for schedule(static)
+    for (long v = 0; v < N; ++v) {
+      const double *Cm = P->Cfield + 36 * v;
+      double em[6];
+      for (int b = 0; b < 6; ++b) em[b] = eps[b * N + v] * (b < 3 ? 1.0 : sqrt(2.0));
+      for (int a = 0; a < 6; ++a) {
+        double acc = 0;
+        for (int b = 0; b < 6; ++b) acc += Cm[6 * a + b] * em[b];
+        acc /= (a < 3 ? 1.0 : sqrt(2.0));
+        if (sig_re_out) sig_re_out[a * N + v] = acc;
+        if (sig_c_out) sig_c_out[a * N + v] = acc;
+      }
+    }
+    return;
+  }
 #pragma omp parallel for schedule(static)
   for (long v = 0; v < N; ++v) {
     double e[3][3];
@@ -511,6 +529,37 @@ done:
     res->true_residual = (bnorm > 0) ? sqrt(frob_dot(r, r, P->N)) / bnorm : 0.0;
   }
   if (w == &own) minres_vecs_free(&own);
+}
+
+/* Operator and MINRES with a stiffness per voxel (the tangent C^{i-1}(x) of eq. galnonlin).
+ * Cfield: [N][36] Mandel matrices.  or_apply_field: y = A_i(x).  or_minres_field: A_i x = b from
+ * x = 0, stopped when |phibar| < tol ||b||; info = (iterations, status, rel_residual, true_residual,
+ * ||b||).  Tensor components in and out, as or_apply. */
+void or_apply_field(const int n[3], const double L[3], int scheme, int nyquist, int stress_mask, const double *Cfield,
+                    const double *x, double *y) {
+  or_problem P;
+  double Z[36] = {0};
+  setup(&P, n, L, scheme, nyquist, stress_mask, NULL, Z, Z);
+  P.Cfield = Cfield;
+  apply_A(&P, x, y);
+  teardown(&P);
+}
+
+void or_minres_field(const int n[3], const double L[3], int scheme, int nyquist, int stress_mask,
+                     const double *Cfield, const double *b, double tol, int maxit, double *x, double *info) {
+  or_problem P;
+  double Z[36] = {0};
+  setup(&P, n, L, scheme, nyquist, stress_mask, NULL, Z, Z);
+  P.Cfield = Cfield;
+  memset(x, 0, sizeof(double) * 6 * P.N);
+  or_result res;
+  minres(&P, b, x, tol, maxit, NULL, &res);
+  info[0] = res.iterations;
+  info[1] = res.status;
+  info[2] = res.rel_residual;
+  info[3] = res.true_residual;
+  info[4] = res.bnorm;
+  teardown(&P);
 }
 
 /* Conjugate gradients (Hestenes & Stiefel) on the same system, for the behavioural comparison. */
