@@ -27,7 +27,8 @@ ABI_SYMBOLS = ("rve_default_options", "rve_supported_length", "rve_validate", "r
                "rve_apply_workspace_bytes", "rve_apply", "rve_profile_enable", "rve_profile_reset", "rve_profile_read",
                "rve_profile_kind_name", "rve_batch_workspace_bytes", "solve_rve_batch", "rve_autotune", "rve_load_tuning", "rve_tuned_tiles", "rve_last_error",
                "rve_last_solve_info", "rve_last_mean_strain", "rve_release_caches", "rve_cache_counts", "solve_rve_noalloc",
-               "rve_noalloc_scratch_bytes", "rve_status_string")
+               "rve_noalloc_scratch_bytes", "rve_status_string", "rve_j2_workspace_bytes", "solve_rve_j2",
+               "rve_j2_return_map")
 
 
 class RveError(RuntimeError):
@@ -48,6 +49,21 @@ class Options(ctypes.Structure):
                 ("max_refine", ctypes.c_int32), ("nyquist", ctypes.c_int32), ("scheme", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("inner_floor", ctypes.c_double), ("inner_safety", ctypes.c_double),
                 ("stress_mask", ctypes.c_int32), ("macro_stress", ctypes.POINTER(ctypes.c_double))]
+
+
+class J2Material(ctypes.Structure):
+    _fields_ = [("young", ctypes.c_double), ("poisson", ctypes.c_double), ("yield_stress", ctypes.c_double)]
+
+
+class J2Options(ctypes.Structure):
+    _fields_ = [("increments", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("newton_tol", ctypes.c_double),
+                ("lin_tol", ctypes.c_double)]
+
+
+class J2Increment(ctypes.Structure):
+    _fields_ = [("strain_mean", ctypes.c_double * 6), ("stress_mean", ctypes.c_double * 6), ("r_newton", ctypes.c_double),
+                ("newton", ctypes.c_int32), ("minres", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class BatchItem(ctypes.Structure):
@@ -103,6 +119,13 @@ def load_library():
     lib.solve_rve_batch.restype = ctypes.c_int
     lib.rve_autotune.argtypes = [gp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t, vp, ctypes.c_char_p, dp]
     lib.rve_autotune.restype = ctypes.c_int
+    lib.rve_j2_workspace_bytes.argtypes = [gp, op]
+    lib.rve_j2_workspace_bytes.restype = ctypes.c_size_t
+    lib.solve_rve_j2.argtypes = [gp, vp, ctypes.POINTER(J2Material), dp, dp, op, ctypes.POINTER(J2Options), vp, vp, vp,
+                                 vp, ctypes.POINTER(J2Increment), vp, ctypes.c_size_t, vp]
+    lib.solve_rve_j2.restype = ctypes.c_int
+    lib.rve_j2_return_map.argtypes = [ctypes.c_int64, vp, ctypes.POINTER(J2Material), vp, vp, vp, vp, vp]
+    lib.rve_j2_return_map.restype = ctypes.c_int
     lib.rve_load_tuning.argtypes = [ctypes.c_char_p]
     lib.rve_load_tuning.restype = ctypes.c_int32
     lib.rve_tuned_tiles.argtypes = [gp, ctypes.c_int32, ip]
@@ -360,6 +383,67 @@ def solve(phi, C_solid, macro_strain, *, C_void=None, L=(1.0, 1.0, 1.0), opt: Op
     del S
     return dict(strain=strain, stress=stress, eff_stress=eff, mean_strain=mean, iterations=its, rel_residual=res,
                 status=int(st))
+
+
+def solve_j2(phi, young: float, poisson: float, yield_stress: float, macro_strain_final, *, increments: int = 20,
+             newton_tol: float = 5e-3, lin_tol: float = 1e-6, max_newton: int = 25, macro_stress_final=None,
+             L=(1.0, 1.0, 1.0), opt: Options | None = None, workspace: Workspace | None = None, check: bool = True,
+             **opt_kw) -> dict:
+    """solve_rve_j2: J2 perfectly plastic solid on the device phase map `phi` (float32 [n0,n1,n2]),
+    load ramp to macro_strain_final (and macro_stress_final on the stress_mask components).
+    Returns dict(strain, stress, plastic_strain [6,*n] FP64, ep_acc [*n], history: list of dicts per
+    increment (strain_mean, stress_mean, newton, minres, r_newton, status), status)."""
+    torch = _torch()
+    lib = load_library()
+    if not (phi.is_cuda and phi.dtype == torch.float32 and phi.dim() == 3 and phi.is_contiguous()):
+        raise ValueError("phi must be a contiguous float32 CUDA tensor of shape (n0, n1, n2)")
+    n = tuple(phi.shape)
+    opt = opt or default_options(**opt_kw)
+    g = make_grid(n, L)
+    mat = J2Material(float(young), float(poisson), float(yield_stress))
+    jo = J2Options(int(increments), int(max_newton), float(newton_tol), float(lin_tol))
+    E = np.ascontiguousarray(np.asarray(macro_strain_final, dtype=np.float64).reshape(6))
+    S = None if macro_stress_final is None else np.ascontiguousarray(np.asarray(macro_stress_final, np.float64).reshape(6))
+    nbytes = lib.rve_j2_workspace_bytes(ctypes.byref(g), ctypes.byref(opt))
+    if nbytes == 0:
+        raise RveError(RVE_EINVAL, "rve_j2_workspace_bytes")
+    ws = (workspace or _default_ws).get(nbytes, phi.device)
+    f = lambda: torch.empty((6,) + n, dtype=torch.float64, device=phi.device)  # noqa: E731
+    strain, stress, eps_p = f(), f(), f()
+    ep = torch.empty(n, dtype=torch.float64, device=phi.device)
+    hist = (J2Increment * int(increments))()
+    cur = torch.cuda.current_stream(phi.device)
+    ss = _solver_stream(torch, phi.device)
+    ss.wait_stream(cur)
+    st = lib.solve_rve_j2(ctypes.byref(g), ctypes.c_void_p(phi.data_ptr()), ctypes.byref(mat), _dp(E),
+                          _dp(S) if S is not None else None, ctypes.byref(opt), ctypes.byref(jo),
+                          ctypes.c_void_p(strain.data_ptr()), ctypes.c_void_p(stress.data_ptr()),
+                          ctypes.c_void_p(eps_p.data_ptr()), ctypes.c_void_p(ep.data_ptr()), hist,
+                          ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), ctypes.c_void_p(ss.cuda_stream))
+    cur.wait_stream(ss)
+    if check and st < 0:
+        raise RveError(st, "solve_rve_j2")
+    history = [dict(strain_mean=np.array(h.strain_mean[:]), stress_mean=np.array(h.stress_mean[:]), newton=h.newton,
+                    minres=h.minres, r_newton=h.r_newton, status=h.status) for h in hist]
+    return dict(strain=strain, stress=stress, plastic_strain=eps_p, ep_acc=ep, history=history, status=int(st))
+
+
+def j2_return_map(phi, young: float, poisson: float, yield_stress: float, strain, plastic_strain):
+    """rve_j2_return_map on device fields (FP64 [6, ...], phi float32): returns (stress [6, ...],
+    tangent data [7, ...]: a and m of C_t = phi (C_e - a I_dev - m m))."""
+    torch = _torch()
+    lib = load_library()
+    nv = int(phi.numel())
+    mat = J2Material(float(young), float(poisson), float(yield_stress))
+    sig = torch.empty_like(strain)
+    tan = torch.empty((7,) + tuple(strain.shape[1:]), dtype=torch.float64, device=strain.device)
+    st = lib.rve_j2_return_map(nv, ctypes.c_void_p(phi.data_ptr()), ctypes.byref(mat),
+                               ctypes.c_void_p(strain.data_ptr()), ctypes.c_void_p(plastic_strain.data_ptr()),
+                               ctypes.c_void_p(sig.data_ptr()), ctypes.c_void_p(tan.data_ptr()),
+                               _stream_ptr(torch, strain.device))
+    if st != RVE_OK:
+        raise RveError(st, "rve_j2_return_map")
+    return sig, tan
 
 
 def solve_batch(rves, C_solid, *, C_void=None, opt: Options | None = None, want_stress: bool = False,

@@ -88,6 +88,11 @@ struct Material {
   int iso_d, iso_0;
   T lam_d, mu2_d, lam_0, mu2_0;
   long long phi_stride;  // voxels between the phase maps of consecutive load cases (0: one map for all)
+  // Tangent of an elastic-plastic solid (P1 instance with TAN = true, eq. Slin): per voxel a and m[6]
+  // in [7][nvox], C_t(x) = phi(x) (Cd - a I_dev - m (x) m), Cd isotropic and C0 = 0; tan_stride values
+  // between consecutive load cases.  nullptr otherwise.
+  const T* tan;
+  long long tan_stride;
 };
 
 // x when A, else y (references of possibly different types, chosen at compile time)
@@ -206,7 +211,7 @@ __device__ __forceinline__ void givens_step(MinresState& S, double sumsq) {
 // ============================================================================ P1
 // grid (ceil(N1/W), N0, ncases), block W*NB threads, dyn. LDS W*max(NA*(NB+1), N+1) complex
 // With `partials` (MINRES iterations): per-block <x, sigma> partials for the Lanczos alpha.
-template <typename T, int NA, int NB>
+template <typename T, int NA, int NB, bool TAN = false>
 __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib,
                                                    int xscale_stride, const float* __restrict__ phi, Material<T> mat,
                                                    cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, GridDims g,
@@ -247,12 +252,34 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
 #pragma unroll
       for (int b = 0; b < 6; ++b) ev[b] = e[b][i];
       const T tr = ev[0] + ev[1] + ev[2];
+      if constexpr (TAN) {
+        // C_t e = phi (Cd e - a dev(e) - (m . e) m), the tangent's data read element by element
+        const T* tp = mat.tan + (long long)cs * mat.tan_stride + row + t + NB * i;
+        T ta = 0, tm[6], md = 0;
 #pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        T sv = 0;
-        if (mat.use_phi) sv = ph[i] * stiff_row(mat.Cd, mat.iso_d, mat.lam_d, mat.mu2_d, a, ev, tr);
-        if (mat.has_c0) sv += stiff_row(mat.C0, mat.iso_0, mat.lam_0, mat.mu2_0, a, ev, tr);
-        sg[a][i] = sv * xs;
+        for (int b = 0; b < 6; ++b) tm[b] = 0;
+        if (row_ok) {
+          ta = tp[0];
+#pragma unroll
+          for (int b = 0; b < 6; ++b) tm[b] = tp[(long long)(1 + b) * g.nvox];
+        }
+#pragma unroll
+        for (int b = 0; b < 6; ++b) md += tm[b] * ev[b];
+        const T tr3 = tr * (T)(1.0 / 3.0);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          const T dv = a < 3 ? ev[a] - tr3 : ev[a];
+          const T sv = stiff_row(mat.Cd, mat.iso_d, mat.lam_d, mat.mu2_d, a, ev, tr) - ta * dv - md * tm[a];
+          sg[a][i] = ph[i] * sv * xs;
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          T sv = 0;
+          if (mat.use_phi) sv = ph[i] * stiff_row(mat.Cd, mat.iso_d, mat.lam_d, mat.mu2_d, a, ev, tr);
+          if (mat.has_c0) sv += stiff_row(mat.C0, mat.iso_0, mat.lam_0, mat.mu2_0, a, ev, tr);
+          sg[a][i] = sv * xs;
+        }
       }
       if (partials) {
 #pragma unroll

@@ -17,7 +17,7 @@ using P5Fn = void (*)(const cx<T>*, T*, const T*, const T*, double*, const cx<T>
 
 template <typename T>
 struct LenKernels {
-  P1Fn<T> p1;
+  P1Fn<T> p1, p1t;  // p1t: with the per-voxel elastic-plastic tangent (Material::tan)
   P2Fn<T> p2f, p2i;
   P3Fn<T> p3, p3_ident;
   P3Fn<T> p3s, p3s_ident;  // components split over two halves of the block
@@ -43,7 +43,7 @@ const LenEntry* find_len(int n, int variant = 0);
 }  // namespace rve
 
 #define RVE_LEN_KERNELS(T_, NA_, NB_)                                                                  \
-  {&rve::k_fwd_axis2<T_, NA_, NB_>, &rve::k_axis1<T_, NA_, NB_, -1>, &rve::k_axis1<T_, NA_, NB_, 1>, \
+  {&rve::k_fwd_axis2<T_, NA_, NB_>, &rve::k_fwd_axis2<T_, NA_, NB_, true>, &rve::k_axis1<T_, NA_, NB_, -1>, &rve::k_axis1<T_, NA_, NB_, 1>, \
    &rve::k_axis0_project<T_, NA_, NB_, false>, &rve::k_axis0_project<T_, NA_, NB_, true>,              \
    &rve::k_axis0_project_split<T_, NA_, NB_, false>, &rve::k_axis0_project_split<T_, NA_, NB_, true>,  \
    &rve::k_axis0_project_split3<T_, NA_, NB_, false>, &rve::k_axis0_project_split3<T_, NA_, NB_, true>, \

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/rve.h"
+#include "../../include/rve_j2.h"
 #include "rve_registry.h"
 
 namespace rve {
@@ -479,7 +480,7 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     const size_t lds = sizeof(cx<T>) * W * std::max(na2 * (nb2 + 1), N2 + 1);
     dim3 grid((g.n1 + W - 1) / W, g.n0, nc);
     prof::begin<T>(prof::P1, s);
-    hipLaunchKernelGGL(K2.p1, grid, dim3(W * nb2), lds, s, x, xscale, (int)(sizeof(MinresState) / sizeof(double)),
+    hipLaunchKernelGGL(mat.tan ? K2.p1t : K2.p1, grid, dim3(W * nb2), lds, s, x, xscale, (int)(sizeof(MinresState) / sizeof(double)),
                        phi, mat, spec, tb.tw[2], g, W, st, uk ? partials : nullptr);
     prof::end(s);
     if (uk) {
@@ -978,8 +979,7 @@ struct SolveRun {
 
   // Tables, right-hand side b = -A(Ebar) + Ghat(0) Sbar with ||b||, and the start x64 (zero or the
   // projected warm start eps0 [nc][6][N] in the solve's field type), r64 = b - A x64.
-  rve_status setup(const void* eps0) {
-    const GridDims& g = pl.g;
+  rve_status setup_tables() {
     rve_status r = build_tables<double>(pl, grid, ws + L.off_tab64, opt->scheme, opt->nyquist, s);
     if (r != RVE_OK) return r;
     tb64 = tables_at<double>(pl, ws + L.off_tab64);
@@ -990,6 +990,36 @@ struct SolveRun {
       tb32 = tables_at<float>(pl, ws + L.off_tab32);
       tb32.stress_mask = opt->stress_mask;
     }
+    return RVE_OK;
+  }
+
+  // A right-hand side the caller has put into b64 (one case): ||b|| (synchronises), x64 = 0,
+  // r64 = b64.  Returns ||b|| in *bnorm; the case is inactive when it is zero.
+  rve_status start_given_rhs(double* bnorm) {
+    const GridDims& g = pl.g;
+    (void)g;
+    hipLaunchKernelGGL((k_lincomb<double, double>), vg, vb, 0, s, r64, b64, 1.0, (const double*)nullptr, 0.0, n6,
+                       part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(nc), dim3(kThreads), 0, s, part, kRedBlocks, sums, 1, 1);
+    double hb = 0.0;
+    HIPCHK(hipMemcpyAsync(&hb, sums, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    hci.assign(nc, CaseInfo{});
+    hci[0].bnorm = hb;
+    hci[0].rnorm = hb;
+    hci[0].r0 = hb;
+    hci[0].active = hb > 0.0 ? 1 : 0;
+    HIPCHK(hipMemcpyAsync(dci, hci.data(), sizeof(CaseInfo) * nc, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, s, x64, n6 * nc);
+    HIPCHK(hipGetLastError());
+    *bnorm = hb;
+    return RVE_OK;
+  }
+
+  rve_status setup(const void* eps0) {
+    const GridDims& g = pl.g;
+    rve_status r = setup_tables();
+    if (r != RVE_OK) return r;
     // macro strains live in the partials buffer's head while b is formed
     double* Ed = part;
     double* Sd = sums + 8 * nc;  // 6 nc doubles of the 16 nc
@@ -1827,6 +1857,241 @@ rve_status solve_rve(const rve_grid* grid, const float* phi, const double* phase
                      double* rel_residual, void* workspace, size_t workspace_bytes, void* hip_stream) {
   return solve_impl(grid, phi, phase_stiffness, macro_strain, n_cases, opt, eps0, strain_out, stress_out, eff_stress,
                     iterations, rel_residual, workspace, workspace_bytes, hip_stream, kSolveDefault);
+}
+
+// ---------------------------------------------------------------------------- J2 plasticity
+// Nonlinear solve of eqs. Slin / galnonlin / galrlin / galrnewton: Newton iterations per increment of a
+// linear load ramp, each linearised problem solved by the MINRES machinery of solve_rve on a
+// right-hand side formed here, with the elastic-plastic tangent fused into P1 (Material::tan).
+static rve_status validate_j2(const rve_j2_material* m, const rve_j2_options* j) {
+  if (!m || !j) return RVE_EINVAL;
+  if (!(std::isfinite(m->young) && m->young > 0.0)) return RVE_EINVAL;
+  if (!(std::isfinite(m->poisson) && m->poisson > -1.0 && m->poisson < 0.5)) return RVE_EINVAL;
+  if (!(std::isfinite(m->yield_stress) && m->yield_stress > 0.0)) return RVE_EINVAL;
+  if (j->increments < 1 || j->max_newton < 1) return RVE_EINVAL;
+  if (!(std::isfinite(j->newton_tol) && j->newton_tol > 0.0) || !(std::isfinite(j->lin_tol) && j->lin_tol > 0.0))
+    return RVE_EINVAL;
+  return RVE_OK;
+}
+
+struct J2Layout {
+  long long eps, eps_t, eps_p, sig, rhs, tan64, tan32, ep, red, total;
+};
+
+static J2Layout j2_layout(const Plan& pl, int prec) {
+  J2Layout J;
+  const long long nv = pl.g.nvox;
+  long long off = make_layout(pl, 1, prec, true).total;
+  auto take = [&](long long bytes) {
+    const long long o = off;
+    off += align_up(bytes, 256);
+    return o;
+  };
+  J.eps = take(6 * nv * 8);
+  J.eps_t = take(6 * nv * 8);
+  J.eps_p = take(6 * nv * 8);
+  J.sig = take(6 * nv * 8);
+  J.rhs = take(6 * nv * 8);
+  J.tan64 = take(7 * nv * 8);
+  J.tan32 = prec == RVE_FP32_MIXED ? take(7 * nv * 4) : 0;
+  J.ep = take(nv * 8);
+  J.red = take(2 * kRedBlocks * 8);
+  J.total = off;
+  return J;
+}
+
+size_t rve_j2_workspace_bytes(const rve_grid* grid, const rve_options* opt) {
+  if (validate_grid(grid) != RVE_OK || validate_options(opt) != RVE_OK) return 0;
+  Plan pl;
+  if (!make_plan(grid, &pl)) return 0;
+  return (size_t)j2_layout(pl, opt->precision).total;
+}
+
+static J2Mat j2_mat(const rve_j2_material* m) {
+  J2Mat j;
+  j.K = m->young / (3.0 * (1.0 - 2.0 * m->poisson));
+  j.mu2 = m->young / (1.0 + m->poisson);
+  j.sy = m->yield_stress;
+  return j;
+}
+
+rve_status rve_j2_return_map(int64_t n_voxels, const float* phi, const rve_j2_material* material, const double* strain,
+                             const double* plastic_strain, double* stress, double* tangent, void* hip_stream) {
+  if (n_voxels < 1 || !phi || !material || !strain || !plastic_strain || (!stress && !tangent)) return RVE_EINVAL;
+  rve_j2_options jo = {1, 1, 1.0, 1.0};
+  rve_status st = validate_j2(material, &jo);
+  if (st != RVE_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipLaunchKernelGGL(k_j2_return, dim3(2048), dim3(kThreads), 0, s, strain, const_cast<double*>(plastic_strain), phi,
+                     j2_mat(material), (long long)n_voxels, stress, tangent, (float*)nullptr, 0, (double*)nullptr);
+  HIPCHK(hipGetLastError());
+  return RVE_OK;
+}
+
+rve_status solve_rve_j2(const rve_grid* grid, const float* phi, const rve_j2_material* material,
+                        const double* macro_strain_final, const double* macro_stress_final, const rve_options* opt,
+                        const rve_j2_options* jopt, double* strain_out, double* stress_out,
+                        double* plastic_strain_out, double* ep_acc_out, rve_j2_increment* history, void* workspace,
+                        size_t workspace_bytes, void* hip_stream) {
+  rve_status st = validate_grid(grid);
+  if (st != RVE_OK) return st;
+  st = validate_options(opt);
+  if (st != RVE_OK) return st;
+  st = validate_j2(material, jopt);
+  if (st != RVE_OK) return st;
+  if (!phi || !macro_strain_final || !history || !workspace) return RVE_EINVAL;
+  for (int a = 0; a < 6; ++a) {
+    if (!std::isfinite(macro_strain_final[a])) return RVE_ENONFINITE;
+    if (macro_stress_final && !std::isfinite(macro_stress_final[a])) return RVE_ENONFINITE;
+  }
+  Plan pl;
+  if (!make_plan(grid, &pl)) return RVE_EUNSUPPORTED_SIZE;
+  const J2Layout J = j2_layout(pl, opt->precision);
+  if ((long long)workspace_bytes < J.total) return RVE_ENOMEM;
+  const J2Mat jm = j2_mat(material);
+  // the solid's elastic stiffness (Mandel), empty phase zero
+  double C[72];
+  memset(C, 0, sizeof(C));
+  const double lam = jm.K - jm.mu2 / 3.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) C[36 + a * 6 + b] = lam;
+  for (int a = 0; a < 6; ++a) C[36 + a * 7] += jm.mu2;
+  rve_options lo = *opt;  // the MINRES tolerance is set per Newton iteration
+  lo.macro_stress = nullptr;
+  const double zero6[6] = {0, 0, 0, 0, 0, 0};
+  hipStream_t s = (hipStream_t)hip_stream;
+  char* ws = (char*)workspace;
+  SolveRun R;
+  st = R.init(grid, phi, 0, C, zero6, nullptr, 1, &lo, ws, workspace_bytes, s);
+  if (st != RVE_OK) return st;
+  StreamCache* cache = cache_acquire(s);
+  CacheLease lease(cache);
+  LoopCtx ctx;
+  ctx.cache = cache;
+  ctx.u2_inline = false;
+  ctx.allow_graph = true;
+  st = R.check_phi();
+  if (st != RVE_OK) return st;
+  st = R.setup_tables();
+  if (st != RVE_OK) return st;
+  const long long nv = pl.g.nvox, n6 = 6 * nv;
+  double* eps = reinterpret_cast<double*>(ws + J.eps);
+  double* eps_t = reinterpret_cast<double*>(ws + J.eps_t);
+  double* eps_p = reinterpret_cast<double*>(ws + J.eps_p);
+  double* sig = reinterpret_cast<double*>(ws + J.sig);
+  double* rhs = reinterpret_cast<double*>(ws + J.rhs);  // -sigma + Sbar before the projection
+  double* tan64 = reinterpret_cast<double*>(ws + J.tan64);
+  float* tan32 = J.tan32 ? reinterpret_cast<float*>(ws + J.tan32) : nullptr;
+  double* ep = reinterpret_cast<double*>(ws + J.ep);
+  double* red = reinterpret_cast<double*>(ws + J.red);
+  R.mat64.tan = tan64;
+  R.mat64.tan_stride = 7 * nv;
+  R.mat32.tan = tan32;
+  R.mat32.tan_stride = 7 * nv;
+  const dim3 vg(kRedBlocks), vb(kThreads);
+  hipLaunchKernelGGL(k_zero<double>, vg, vb, 0, s, eps, n6);
+  hipLaunchKernelGGL(k_zero<double>, vg, vb, 0, s, eps_p, n6);
+  hipLaunchKernelGGL(k_zero<double>, vg, vb, 0, s, ep, nv);
+  HIPCHK(hipGetLastError());
+  double Ef[6], Sf[6], Et[6] = {0, 0, 0, 0, 0, 0};
+  for (int a = 0; a < 6; ++a) {
+    const bool sc = (opt->stress_mask >> a) & 1;
+    Ef[a] = sc ? 0.0 : macro_strain_final[a];
+    Sf[a] = (sc && macro_stress_final) ? macro_stress_final[a] : 0.0;
+  }
+  double* Sd = R.sums + 8;  // the macroscopic stress of the increment, read by k_rhs
+  const bool fp32 = opt->precision == RVE_FP32_MIXED;
+  std::vector<double> hred(2 * kRedBlocks), hsum(12);
+  rve_status worst = RVE_OK;
+  auto field_mean = [&](const double* f, double* out6) -> rve_status {
+    hipLaunchKernelGGL(k_field_sums, dim3(kRedBlocks, 1), dim3(kThreads), 0, s, f, nv, R.part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(6), dim3(kThreads), 0, s, R.part, kRedBlocks, red, 1, 0);
+    HIPCHK(hipMemcpyAsync(out6, red, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int a = 0; a < 6; ++a) out6[a] /= (double)nv;
+    return RVE_OK;
+  };
+  for (int inc = 1; inc <= jopt->increments; ++inc) {
+    rve_j2_increment& H = history[inc - 1];
+    memset(&H, 0, sizeof(H));
+    double Eb[6], Sb[6];
+    Vec6 dE;
+    for (int a = 0; a < 6; ++a) {
+      Eb[a] = Ef[a] * inc / jopt->increments;
+      Sb[a] = Sf[a] * inc / jopt->increments;
+      dE.v[a] = Eb[a] - Et[a];
+    }
+    HIPCHK(hipMemcpyAsync(eps_t, eps, n6 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_add_uniform, vg, vb, 0, s, eps, dE, nv);
+    double b0 = -1.0, r_newton = INFINITY;
+    for (int it = 1; it <= jopt->max_newton; ++it) {
+      // sigma and tangent at eps^{i-1}; b_i = -G(sigma - Sbar)
+      hipLaunchKernelGGL(k_j2_return, vg, vb, 0, s, eps, eps_p, phi, jm, nv, sig, tan64, tan32, 0, (double*)nullptr);
+      HIPCHK(hipMemcpyAsync(Sd, Sb, 6 * sizeof(double), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_rhs, dim3(kRedBlocks, 1), dim3(kThreads), 0, s, rhs, sig, Sd, nv, R.part);
+      apply_op<double>(R.pl, 1, rhs, nullptr, phi, R.ident64, R.tb64, R.spec64, R.b64, nullptr, nullptr, nullptr,
+                       nullptr, 0, s);
+      HIPCHK(hipGetLastError());
+      double bn = 0.0;
+      st = R.start_given_rhs(&bn);
+      if (st != RVE_OK) return st;
+      if (b0 < 0.0) b0 = bn;
+      H.newton = it;
+      if (bn > jopt->lin_tol * b0 && bn > 0.0) {
+        lo.tol = jopt->lin_tol * b0 / bn;
+        const int sweeps = fp32 ? lo.max_refine : 1;
+        for (int sw = 0; sw < sweeps; ++sw) {
+          bool any = false;
+          st = R.sweep_begin(&any);
+          if (st != RVE_OK) return st;
+          if (fp32 && !any) break;
+          st = fp32 ? minres_loop<float>(R.pl, 1, R.B32, phi, R.mat32, R.tb32, R.spec32, R.dst, R.part, lo.max_iter,
+                                         lo.check_every, s, ctx)
+                    : minres_loop<double>(R.pl, 1, R.B64, phi, R.mat64, R.tb64, R.spec64, R.dst, R.part, lo.max_iter,
+                                          lo.check_every, s, ctx);
+          if (st != RVE_OK) return st;
+          st = R.sweep_end();
+          if (st != RVE_OK) return st;
+        }
+        HIPCHK(hipMemcpyAsync(R.hci.data(), R.dci, sizeof(CaseInfo), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        H.minres += R.hci[0].iters;
+        if (R.hci[0].status == RVE_ENONFINITE) return RVE_ENONFINITE;
+        // eps^i = eps^{i-1} + d
+        hipLaunchKernelGGL((k_lincomb<double, double>), dim3(kRedBlocks, 1), vb, 0, s, eps, eps, 1.0, R.x64, 1.0, n6,
+                           R.part);
+      }
+      // eq. galrnewton: |d|_inf / |eps^i - eps^t|_inf (d = x64, zero when no MINRES ran)
+      hipLaunchKernelGGL(k_absmax2, vg, vb, 0, s, R.x64, eps, eps_t, n6, red);
+      HIPCHK(hipMemcpyAsync(hred.data(), red, 2 * kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double dmax = 0.0, emax = 0.0;
+      for (int b = 0; b < kRedBlocks; ++b) {
+        dmax = std::max(dmax, hred[2 * b]);
+        emax = std::max(emax, hred[2 * b + 1]);
+      }
+      r_newton = emax > 0.0 ? dmax / emax : 0.0;
+      if (r_newton <= jopt->newton_tol) break;
+    }
+    H.r_newton = r_newton;
+    H.status = r_newton <= jopt->newton_tol ? 0 : 1;
+    if (H.status) worst = RVE_NOT_CONVERGED;
+    // accept: stress at eps^i, plastic strain and its accumulated norm updated
+    hipLaunchKernelGGL(k_j2_return, vg, vb, 0, s, eps, eps_p, phi, jm, nv, sig, (double*)nullptr, (float*)nullptr, 1, ep);
+    HIPCHK(hipGetLastError());
+    st = field_mean(eps, H.strain_mean);
+    if (st != RVE_OK) return st;
+    st = field_mean(sig, H.stress_mean);
+    if (st != RVE_OK) return st;
+    for (int a = 0; a < 6; ++a) Et[a] = Eb[a];
+  }
+  if (strain_out) HIPCHK(hipMemcpyAsync(strain_out, eps, n6 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (stress_out) HIPCHK(hipMemcpyAsync(stress_out, sig, n6 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (plastic_strain_out)
+    HIPCHK(hipMemcpyAsync(plastic_strain_out, eps_p, n6 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (ep_acc_out) HIPCHK(hipMemcpyAsync(ep_acc_out, ep, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return worst;
 }
 
 // ---------------------------------------------------------------------------- no-allocation entry point

@@ -389,4 +389,103 @@ __global__ void k_check_phi(const float* phi, long long n, int* bad) {
   if (nr) atomicAdd(&bad[1], nr);
 }
 
+// ---------------------------------------------------------------------------- J2 plasticity (eq. Slin)
+// Isotropic elastic, perfectly plastic (von Mises) solid of bulk modulus K, shear modulus mu2/2 and
+// yield stress sy; a voxel carries phi times the solid's stress and tangent.
+struct J2Mat {
+  double K, mu2, sy;
+};
+struct Vec6 {
+  double v[6];
+};
+
+// Radial return at every voxel from the plastic strain eps_p of the last accepted increment:
+// s = mu2 dev(eps - eps_p), q = sqrt(3/2)|s|; elastic when q <= sy, else the deviator is scaled by
+// theta = sy/q and (1 - theta) dev(eps - eps_p) is the plastic strain increment.  Writes sigma and the
+// tangent data of P1 (a = mu2 (1 - theta), m = sqrt(mu2 theta) s/|s|; zero when elastic) in FP64 and
+// FP32 ([7][nvox]; each may be null).  accept: eps_p += increment, ep_acc += |increment|.
+__global__ void k_j2_return(const double* __restrict__ eps, double* eps_p, const float* __restrict__ phi, J2Mat jm,
+                            long long nvox, double* __restrict__ sig, double* __restrict__ tan64,
+                            float* __restrict__ tan32, int accept, double* __restrict__ ep_acc) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (long long)gridDim.x * blockDim.x) {
+    double ee[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) ee[a] = eps[a * nvox + v] - eps_p[a * nvox + v];
+    const double tr = ee[0] + ee[1] + ee[2];
+    double dev[6], s[6], s2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      dev[a] = a < 3 ? ee[a] - tr / 3.0 : ee[a];
+      s[a] = jm.mu2 * dev[a];
+      s2 += s[a] * s[a];
+    }
+    const double sn = sqrt(s2);
+    const double q = sqrt(1.5) * sn;
+    const bool plastic = q > jm.sy;
+    const double theta = plastic ? jm.sy / q : 1.0;
+    const double ph = (double)phi[v];
+    if (sig) {
+#pragma unroll
+      for (int a = 0; a < 6; ++a) sig[a * nvox + v] = ((a < 3 ? jm.K * tr : 0.0) + theta * s[a]) * ph;
+    }
+    const double ta = plastic ? jm.mu2 * (1.0 - theta) : 0.0;
+    const double mf = plastic ? sqrt(jm.mu2 * theta) / sn : 0.0;
+    if (tan64) {
+      tan64[v] = ta;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) tan64[(1 + a) * nvox + v] = mf * s[a];
+    }
+    if (tan32) {
+      tan32[v] = (float)ta;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) tan32[(1 + a) * nvox + v] = (float)(mf * s[a]);
+    }
+    if (accept && plastic) {
+      double d2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const double d = (1.0 - theta) * dev[a];
+        eps_p[a * nvox + v] += d;
+        d2 += d * d;
+      }
+      ep_acc[v] += sqrt(d2);
+    }
+  }
+}
+
+// x += c (a uniform Mandel vector) at every voxel
+__global__ void k_add_uniform(double* x, Vec6 c, long long nvox) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < 6 * nvox; i += (long long)gridDim.x * blockDim.x)
+    x[i] += c.v[i / nvox];
+}
+
+// per-block maxima of |d| and |e - et| over n values: partials[2 b], partials[2 b + 1]
+__global__ void k_absmax2(const double* __restrict__ d, const double* __restrict__ e, const double* __restrict__ et,
+                          long long n, double* partials) {
+  __shared__ double red[2][kThreads / 64];
+  double m1 = 0.0, m2 = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    m1 = fmax(m1, fabs(d[i]));
+    m2 = fmax(m2, fabs(e[i] - et[i]));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m1 = fmax(m1, __shfl_xor(m1, o));
+    m2 = fmax(m2, __shfl_xor(m2, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = m1;
+    red[1][threadIdx.x >> 6] = m2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      m1 = fmax(m1, red[0][w]);
+      m2 = fmax(m2, red[1][w]);
+    }
+    partials[2 * blockIdx.x] = m1;
+    partials[2 * blockIdx.x + 1] = m2;
+  }
+}
+
 }  // namespace rve
