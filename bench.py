@@ -60,6 +60,15 @@ def workload(name):
                "seeds": "1000+i", "load": "6 unit Mandel strains per RVE", "load_cases": 6, "tol": 1e-6,
                "precision": "fp32-mixed", "voxels_total": int(sum(np.prod(nn) for nn, _ in rv))}
         return [tuple(nn) for nn, _ in rv], phis, np.eye(6), cfg
+    elif name == "octet_j2":
+        # the paper's nonlinear test: octet VA map at relative density 0.1 and about 15 voxels per strut
+        # diameter (162^3), uniaxial compression to -10 % in 20 increments, lateral stress-free
+        n = (162, 162, 162)
+        cfg = {"workload": "octet_j2", "grid": list(n), "rho_target": 0.10, "representation": "VA",
+               "material": {"young_MPa": 1700.0, "poisson": 0.4, "yield_MPa": 70.0},
+               "load": "uniaxial compression eps11 -> -0.1, sigma_22..12 = 0", "increments": 20,
+               "newton_tol": 5e-3, "lin_tol": 1e-6, "precision": "fp32-mixed"}
+        return n, None, None, cfg
     elif name == "density_study":
         cfg = {"workload": "density_study", "rho_target": 0.1, "timed": "phase-field smoothening (PFS) of the "
                "octet at 108^3 coarse voxels on its 540^3 fine grid (ratio 5), FP64",
@@ -201,6 +210,8 @@ def main():
         return bench_batch(args, n, phi, E, cfg, C1)
     if cfg["workload"] == "density_study":
         return bench_density(args, cfg)
+    if cfg["workload"] == "octet_j2":
+        return bench_j2(args, n, cfg)
     log(f"workload {cfg['workload']} built in {time.time() - t0:.1f}s, rho={cfg['rho_actual']:.5f}")
     prec = rve.FP64 if cfg["precision"] == "fp64" else rve.FP32_MIXED
     d = torch.as_tensor(phi, device="cuda:0")
@@ -347,6 +358,112 @@ def main():
             "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64" if prec == rve.FP64 else "f32", "data": "synthetic", "config": cfg,
             "roofline": roof, "cpu_baseline": cpu, "learned_vs_plain": learned, "kernels": kernels}
+    print(json.dumps(line), flush=True)
+
+
+def bench_j2(args, n, cfg):
+    """Nonlinear J2 ramp: wall time of the whole stress-strain curve (Newton + MINRES, FP32-mixed),
+    MINRES voxel-iterations per second over it, per-kernel times of a profiled two-increment ramp,
+    the stress-strain curve, and the oracle's per-voxel-tangent MINRES iterations as CPU baseline."""
+    import torch
+    import paper_2110_00733_amd as rve
+    from paper_2110_00733_amd import density_study as ds, geometry as geo
+    import lattice_inputs as li
+    m = cfg["material"]
+    t0 = time.time()
+    r = ds.target_radius(cfg["rho_target"])
+    S = li.octet_struts(r)
+    phi64, phi = geo.phase_map(n, S, geo.VA, want_f32=True)
+    cfg["radius"] = r
+    cfg["rho_actual"] = float(phi64.mean().item())
+    cfg["voxels_per_diameter"] = round(2 * r * n[0], 2)
+    del phi64
+    log(f"octet VA map {n} radius {r:.6f} rho {cfg['rho_actual']:.5f} built in {time.time() - t0:.1f}s")
+    prec = rve.FP32_MIXED if cfg["precision"] == "fp32-mixed" else rve.FP64
+    if not args.no_autotune:
+        rve.autotune(n, n_cases=1, precision=prec)
+        if prec == rve.FP32_MIXED:
+            rve.autotune(n, n_cases=1, precision=rve.FP64)
+    ws = rve.Workspace()
+    E = [-0.1, 0, 0, 0, 0, 0]
+    kw = dict(increments=cfg["increments"], newton_tol=cfg["newton_tol"], lin_tol=cfg["lin_tol"], stress_mask=0b111110,
+              macro_stress_final=np.zeros(6), precision=prec, workspace=ws, max_iter=5000)
+
+    def ramp(**over):
+        k = dict(kw)
+        k.update(over)
+        return rve.solve_j2(phi, m["young_MPa"], m["poisson"], m["yield_MPa"], E, **k)
+
+    for _ in range(args.warmup):
+        ramp(increments=2)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    out = ramp()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - ts
+    hist = out["history"]
+    minres = sum(h["minres"] for h in hist)
+    nvox = int(np.prod(n))
+    value = nvox * minres / wall
+    curve = [[round(float(h["strain_mean"][0]), 5), round(float(h["stress_mean"][0]), 4)] for h in hist]
+    log(f"ramp {wall:.2f}s, newton {[h['newton'] for h in hist]}, minres {minres}, status {out['status']}")
+    # per-kernel: a profiled two-increment ramp (launches one at a time)
+    rve.profile_reset()
+    rve.profile_enable(True)
+    ramp(increments=2)
+    torch.cuda.synchronize()
+    rve.profile_enable(False)
+    prof = rve.profile_read()
+    kernels = {}
+    elem = 4 if prec == rve.FP32_MIXED else 8
+    for k, (ms, cnt) in prof.items():
+        if cnt == 0 or k[0] in "GM":
+            continue
+        is64 = k.endswith("_f64")
+        own = is64 == (elem == 8)
+        ab = algorithmic_bytes(k[:-4] if is64 else k, n, 1, 8 if is64 else 4, plain_apply=not own)
+        if k.startswith("P1_"):
+            ab += 7 * nvox * (8 if is64 else 4)  # the tangent's data
+        avg = ms / cnt
+        kernels[k] = {"total_ms": ms, "launches": cnt, "avg_us": 1e3 * avg, "alg_bytes": ab,
+                      "gbs": (ab / (avg * 1e-3) / 1e9) if ab else None}
+    log(json.dumps({k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kernels.items()}))
+    alone = [k for k in kernels if kernels[k]["alg_bytes"] and not k.startswith("U2_")]
+    dom = max(alone, key=lambda k: kernels[k]["total_ms"])
+    kd = kernels[dom]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(kd["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "avg_us": round(kd["avg_us"], 2),
+            "alg_bytes_per_launch": kd["alg_bytes"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import plasticity as opl
+        nn = (96, 96, 96)
+        p96 = geo.phase_map(nn, S, geo.VA).cpu().numpy()
+        eps = np.zeros((6,) + nn)
+        eps[0] = -0.05
+        sig, Ct, _, _ = opl.return_map(eps, np.zeros_like(eps), p96, m["young_MPa"], m["poisson"], m["yield_MPa"])
+        b = -oracle.project(nn, sig, stress_mask=0b111110)
+        tc = time.perf_counter()
+        opl.minres_tangent(nn, Ct, b, 1e-30, 3, stress_mask=0b111110)
+        secs = time.perf_counter() - tc
+        cpu = {"value": int(np.prod(nn)) * 3 / secs, "unit": "voxel-iterations/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"3 FP64 MINRES iterations with the per-voxel tangent (a 6x6 matrix per voxel) of the CPU "
+                         f"oracle on the same octet at 96^3, plastic state at 5 % compression, {secs:.1f} s "
+                         f"including setup and the final true-residual apply"}
+        log(f"cpu baseline {cpu['value']:.3e} voxel-it/s")
+    cfg.update({"wall_s": round(wall, 3), "newton_per_increment": [h["newton"] for h in hist],
+                "minres_per_increment": [h["minres"] for h in hist], "minres_total": minres,
+                "status": out["status"], "stress_strain_curve": curve,
+                "plastic_voxel_fraction": float((out["ep_acc"] > 0).double().mean().item()),
+                "parallelism": "single-gpu"})
+    line = {"metric": "J2 stress-strain curve: MINRES voxel-iterations/s and wall time (20 increments)",
+            "value": value, "unit": "voxel-iterations/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+            "ms_per_step": 1e3 * wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32" if prec == rve.FP32_MIXED else "f64", "data": "synthetic", "config": cfg,
+            "roofline": roof, "cpu_baseline": cpu, "kernels": kernels}
     print(json.dumps(line), flush=True)
 
 
