@@ -28,7 +28,7 @@ ABI_SYMBOLS = ("rve_default_options", "rve_supported_length", "rve_validate", "r
                "rve_profile_kind_name", "rve_batch_workspace_bytes", "solve_rve_batch", "rve_autotune", "rve_load_tuning", "rve_tuned_tiles", "rve_last_error",
                "rve_last_solve_info", "rve_last_mean_strain", "rve_release_caches", "rve_cache_counts", "solve_rve_noalloc",
                "rve_noalloc_scratch_bytes", "rve_status_string", "rve_j2_workspace_bytes", "solve_rve_j2",
-               "rve_j2_return_map")
+               "rve_j2_return_map", "rve_modbfft_workspace_bytes", "solve_rve_modbfft")
 
 
 class RveError(RuntimeError):
@@ -64,6 +64,15 @@ class J2Increment(ctypes.Structure):
     _fields_ = [("strain_mean", ctypes.c_double * 6), ("stress_mean", ctypes.c_double * 6), ("r_newton", ctypes.c_double),
                 ("newton", ctypes.c_int32), ("minres", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("pad", ctypes.c_int32)]
+
+
+MODBFFT_PASSES = ("expand", "ifft_axis0", "ifft_axis1", "axis2_stress", "fft_axis1", "fft_axis0", "contract",
+                  "cg_update")
+
+
+class ModbfftStats(ctypes.Structure):
+    _fields_ = [("timed", ctypes.c_int32), ("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("pass_ms", ctypes.c_double * 8), ("pass_launches", ctypes.c_int64 * 8)]
 
 
 class BatchItem(ctypes.Structure):
@@ -126,6 +135,11 @@ def load_library():
     lib.solve_rve_j2.restype = ctypes.c_int
     lib.rve_j2_return_map.argtypes = [ctypes.c_int64, vp, ctypes.POINTER(J2Material), vp, vp, vp, vp, vp]
     lib.rve_j2_return_map.restype = ctypes.c_int
+    lib.rve_modbfft_workspace_bytes.argtypes = [gp]
+    lib.rve_modbfft_workspace_bytes.restype = ctypes.c_size_t
+    lib.solve_rve_modbfft.argtypes = [gp, vp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp, dp,
+                                      ctypes.POINTER(ModbfftStats), vp, ctypes.c_size_t, vp]
+    lib.solve_rve_modbfft.restype = ctypes.c_int
     lib.rve_load_tuning.argtypes = [ctypes.c_char_p]
     lib.rve_load_tuning.restype = ctypes.c_int32
     lib.rve_tuned_tiles.argtypes = [gp, ctypes.c_int32, ip]
@@ -426,6 +440,47 @@ def solve_j2(phi, young: float, poisson: float, yield_stress: float, macro_strai
     history = [dict(strain_mean=np.array(h.strain_mean[:]), stress_mean=np.array(h.stress_mean[:]), newton=h.newton,
                     minres=h.minres, r_newton=h.r_newton, status=h.status) for h in hist]
     return dict(strain=strain, stress=stress, plastic_strain=eps_p, ep_acc=ep, history=history, status=int(st))
+
+
+def solve_modbfft(phi, C_solid, macro_strain, *, alpha: float | None = None, tol: float = 1e-6,
+                  max_iter: int = 5000, L=(1.0, 1.0, 1.0), want_fields: bool = True, timed: bool = False,
+                  workspace: Workspace | None = None, check: bool = True) -> dict:
+    """solve_rve_modbfft (one macroscopic strain, FP64): returns dict(strain, stress [6,*n] FP64 or None,
+    eff_stress [6], iterations, rel_residual, alpha, pass_ms {pass: ms} when timed, status)."""
+    torch = _torch()
+    lib = load_library()
+    if not (phi.is_cuda and phi.dtype == torch.float32 and phi.dim() == 3 and phi.is_contiguous()):
+        raise ValueError("phi must be a contiguous float32 CUDA tensor of shape (n0, n1, n2)")
+    n = tuple(phi.shape)
+    g = make_grid(n, L)
+    C = np.ascontiguousarray(np.asarray(C_solid, dtype=np.float64).reshape(36))
+    E = np.ascontiguousarray(np.asarray(macro_strain, dtype=np.float64).reshape(6))
+    nbytes = lib.rve_modbfft_workspace_bytes(ctypes.byref(g))
+    if nbytes == 0:
+        raise RveError(RVE_EUNSUPPORTED_SIZE, "rve_modbfft_workspace_bytes")
+    ws = (workspace or _default_ws).get(nbytes, phi.device)
+    strain = torch.empty((6,) + n, dtype=torch.float64, device=phi.device) if want_fields else None
+    stress = torch.empty((6,) + n, dtype=torch.float64, device=phi.device) if want_fields else None
+    eff = np.zeros(6)
+    st = ModbfftStats()
+    st.timed = 1 if timed else 0
+    cur = torch.cuda.current_stream(phi.device)
+    ss = _solver_stream(torch, phi.device)
+    ss.wait_stream(cur)
+    rc = lib.solve_rve_modbfft(ctypes.byref(g), ctypes.c_void_p(phi.data_ptr()), _dp(C), _dp(E),
+                               float(alpha) if alpha is not None else 0.0, float(tol), int(max_iter),
+                               ctypes.c_void_p(strain.data_ptr()) if strain is not None else None,
+                               ctypes.c_void_p(stress.data_ptr()) if stress is not None else None, _dp(eff),
+                               ctypes.byref(st), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                               ctypes.c_void_p(ss.cuda_stream))
+    cur.wait_stream(ss)
+    if check and rc < 0:
+        raise RveError(rc, "solve_rve_modbfft")
+    out = dict(strain=strain, stress=stress, eff_stress=eff, iterations=int(st.iterations),
+               rel_residual=float(st.rel_residual), alpha=float(st.alpha), status=int(rc))
+    if timed:
+        out["pass_ms"] = {k: (float(st.pass_ms[i]), int(st.pass_launches[i])) for i, k in enumerate(MODBFFT_PASSES)}
+    return out
 
 
 def j2_return_map(phi, young: float, poisson: float, yield_stress: float, strain, plastic_strain):

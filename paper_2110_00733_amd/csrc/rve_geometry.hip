@@ -28,6 +28,7 @@
 #include "rve.h"
 #include "rve_device.h"
 #include "rve_geometry.h"
+#include "rve_lds_fft.h"
 
 namespace rve {
 void set_last_error(const char* text);
@@ -43,18 +44,7 @@ using rve::cx;
 using rve::DFT;
 using rve::mk;
 using C = cx<double>;
-
-constexpr int kThreads = 256;
-constexpr int kMaxStages = 10;
-constexpr int kStridedTile = 4096;  // complex elements of a strided-axis LDS tile (64 KiB)
-constexpr int kRowTile = 2048;      // complex elements of a row-pass LDS tile (32 KiB)
-constexpr int kStridedSlots = kStridedTile / kThreads;
-constexpr int kRowSlots = kRowTile / kThreads;
-
-struct FftPlan {
-  int n, stages;
-  int radix[kMaxStages];
-};
+using namespace rvfft;
 
 // a strut ready for the distance: midpoint and half axis in length units, |half|^2, radius
 struct StrutPrep {
@@ -158,67 +148,6 @@ __global__ __launch_bounds__(kThreads) void k_phase_map(const rve_strut* __restr
     }
     if (phi) phi[v] = val;
     if (phi32) phi32[v] = (float)val;
-  }
-}
-
-// ------------------------------------------------------------------ LDS transforms
-// twiddles exp(-2 pi i k / N) and the digit-reversed position of every input index
-__global__ void k_fft_tables(C* __restrict__ tw, int* __restrict__ rev, FftPlan P) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < P.n; k += gridDim.x * blockDim.x) {
-    double s, c;
-    sincospi(2.0 * (double)k / (double)P.n, &s, &c);
-    tw[k] = mk<double>(c, -s);
-    // input index k = sum_q p_q r_q (r_q = N / (R_1...R_q)) goes to sum_q p_q (R_1...R_{q-1})
-    int pos = 0, rem = k, lp = 1, rq = P.n;
-    for (int q = 0; q < P.stages; ++q) {
-      rq /= P.radix[q];
-      const int p = rem / rq;
-      rem -= p * rq;
-      pos += p * lp;
-      lp *= P.radix[q];
-    }
-    rev[k] = pos;
-  }
-}
-
-template <int R, int S>
-__device__ __forceinline__ void butterfly(C* buf, int base, int L, int tw_stride, int w, const C* __restrict__ tw,
-                                          int step) {
-  C a[R];
-#pragma unroll
-  for (int p = 0; p < R; ++p) a[p] = buf[(base + p * L) * tw_stride + w];
-#pragma unroll
-  for (int p = 1; p < R; ++p) {
-    C t = tw[p * step];
-    if (S > 0) t.im = -t.im;
-    a[p] = cmul(a[p], t);
-  }
-  DFT<R, S, double>::run(a);
-#pragma unroll
-  for (int m = 0; m < R; ++m) buf[(base + m * L) * tw_stride + w] = a[m];
-}
-
-// In-place transform of npen pencils stored element-major (element e of pencil w at buf[e*npen + w]),
-// input at digit-reversed positions, output in natural order; S = -1 forward, +1 inverse
-// (unnormalised).  Every stage ends with a barrier; the caller orders the loads before it.
-template <int S>
-__device__ void lds_fft(C* buf, int npen, const FftPlan& P, const C* __restrict__ tw) {
-  int L = 1;
-  for (int q = 0; q < P.stages; ++q) {
-    const int R = P.radix[q];
-    const int Lq = L * R, r = P.n / Lq, nb = P.n / R;
-    for (int idx = threadIdx.x; idx < nb * npen; idx += blockDim.x) {
-      const int w = idx % npen, b = idx / npen;
-      const int j = b % L, base = (b / L) * Lq + j;
-      switch (R) {
-        case 4: butterfly<4, S>(buf, base, L, npen, w, tw, j * r); break;
-        case 2: butterfly<2, S>(buf, base, L, npen, w, tw, j * r); break;
-        case 3: butterfly<3, S>(buf, base, L, npen, w, tw, j * r); break;
-        default: butterfly<5, S>(buf, base, L, npen, w, tw, j * r); break;
-      }
-    }
-    __syncthreads();
-    L = Lq;
   }
 }
 
@@ -458,24 +387,6 @@ __global__ __launch_bounds__(kThreads) void k_c2r_coarsen(const C* __restrict__ 
 }
 
 // ------------------------------------------------------------------ host side
-static bool make_plan(int n, FftPlan& P) {
-  if (n < 1 || n > RVE_GEOMETRY_MAX_FINE) return false;
-  P.n = n;
-  P.stages = 0;
-  int m = n;
-  const int order[4] = {4, 2, 3, 5};
-  for (int oi = 0; oi < 4; ++oi) {
-    const int R = order[oi];
-    while (m % R == 0 && m > 1) {
-      if (P.stages == kMaxStages) return false;
-      P.radix[P.stages++] = R;
-      m /= R;
-    }
-  }
-  for (int q = P.stages; q < kMaxStages; ++q) P.radix[q] = 1;
-  return m == 1;
-}
-
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static bool finite3(const double* L) {
