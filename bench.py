@@ -69,6 +69,14 @@ def workload(name):
                "load": "uniaxial compression eps11 -> -0.1, sigma_22..12 = 0", "increments": 20,
                "newton_tol": 5e-3, "lin_tol": 1e-6, "precision": "fp32-mixed"}
         return n, None, None, cfg
+    elif name == "octet_modbfft":
+        # the paper's solver comparison: plain-voxel octet at density 0.1 and about 20 voxels per strut
+        # diameter (216^3, the paper's 215^3), uniaxial strain, tolerance 1e-6; MoDBFFT (FP64 CG) beside
+        # the Galerkin MINRES solver on the same map
+        n = (216, 216, 216)
+        cfg = {"workload": "octet_modbfft", "grid": list(n), "rho_target": 0.10, "representation": "PV",
+               "load": "eps11=1e-3", "tol": 1e-6, "alpha": "1e-4 E", "precision": "fp64"}
+        return n, None, None, cfg
     elif name == "density_study":
         cfg = {"workload": "density_study", "rho_target": 0.1, "timed": "phase-field smoothening (PFS) of the "
                "octet at 108^3 coarse voxels on its 540^3 fine grid (ratio 5), FP64",
@@ -212,6 +220,8 @@ def main():
         return bench_density(args, cfg)
     if cfg["workload"] == "octet_j2":
         return bench_j2(args, n, cfg)
+    if cfg["workload"] == "octet_modbfft":
+        return bench_modbfft(args, n, cfg, C1)
     log(f"workload {cfg['workload']} built in {time.time() - t0:.1f}s, rho={cfg['rho_actual']:.5f}")
     prec = rve.FP64 if cfg["precision"] == "fp64" else rve.FP32_MIXED
     d = torch.as_tensor(phi, device="cuda:0")
@@ -361,6 +371,90 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def bench_modbfft(args, n, cfg, C1):
+    """MoDBFFT solve (FP64 CG) on a plain-voxel octet: wall time to the tolerance, CG voxel-iterations/s,
+    per-pass times of a second, timed solve, the roofline of the longest pass, the Galerkin solver on the
+    same map for comparison, and the oracle's CG iterations as CPU baseline."""
+    import torch
+    import paper_2110_00733_amd as rve
+    from paper_2110_00733_amd import density_study as ds, geometry as geo
+    import lattice_inputs as li
+    r = ds.target_radius(cfg["rho_target"])
+    S = li.octet_struts(r)
+    phi64, phi = geo.phase_map(n, S, geo.PV, want_f32=True)
+    cfg.update({"radius": r, "rho_actual": float(phi64.mean().item()), "voxels_per_diameter": round(2 * r * n[0], 2)})
+    del phi64
+    E = li.uniaxial_strain(1e-3)
+    ws = rve.Workspace()
+    for _ in range(args.warmup):
+        rve.solve_modbfft(phi, C1, E, tol=cfg["tol"], max_iter=200, workspace=ws, check=False)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    out = rve.solve_modbfft(phi, C1, E, tol=cfg["tol"], max_iter=5000, workspace=ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - ts
+    its = out["iterations"]
+    nvox = int(np.prod(n))
+    log(f"modbfft: {its} iterations, {wall:.2f}s, residual {out['rel_residual']:.2e}, <s11> {out['eff_stress'][0]:.4e}")
+    prof = rve.solve_modbfft(phi, C1, E, tol=cfg["tol"], max_iter=min(its, 60), workspace=ws, timed=True, check=False)
+    K = n[2] // 2 + 1
+    comp = n[0] * n[1] * K * 16  # one component of the FP64 half spectrum
+    alg = {"expand": 3 * comp + 9 * comp, "ifft_axis0": 18 * comp, "ifft_axis1": 18 * comp,
+           "axis2_stress": 18 * comp + 4 * nvox, "fft_axis1": 18 * comp, "fft_axis0": 18 * comp,
+           "contract": 9 * comp + 3 * comp + 3 * comp, "cg_update": 4 * 3 * comp + 2 * 3 * comp + 2 * 3 * comp}
+    kernels = {}
+    for k, (ms, cnt) in prof["pass_ms"].items():
+        if cnt:
+            avg = ms / cnt
+            kernels[k] = {"avg_us": round(1e3 * avg, 2), "launches": cnt, "alg_bytes": alg[k],
+                          "gbs": round(alg[k] / (avg * 1e-3) / 1e9, 1)}
+    log(json.dumps(kernels))
+    dom = max((k for k in kernels if k != "cg_update"), key=lambda k: kernels[k]["avg_us"])
+    kd = kernels[dom]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "avg_us": kd["avg_us"],
+            "alg_bytes_per_launch": kd["alg_bytes"],
+            "iteration_bytes": sum(alg.values()),
+            "iteration_frac": round(sum(alg.values()) * its / wall / 1e9 / HBM_PEAK_GBS, 4)}
+    # the Galerkin MINRES solver on the same plain-voxel map (FP32-mixed and FP64)
+    gal = {}
+    for name, prec in (("galerkin_fp32_mixed", rve.FP32_MIXED), ("galerkin_fp64", rve.FP64)):
+        if not args.no_autotune:
+            rve.autotune(n, n_cases=1, precision=prec)
+        rve.solve(phi, C1, E[None], tol=cfg["tol"], precision=prec, workspace=ws, want_stress=False)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        o = rve.solve(phi, C1, E[None], tol=cfg["tol"], precision=prec, workspace=ws, want_stress=False)
+        torch.cuda.synchronize()
+        gal[name] = {"wall_s": round(time.perf_counter() - tg, 4), "iterations": int(o["iterations"][0]),
+                     "eff_stress_11": float(o["eff_stress"][0][0])}
+        log(f"{name}: {gal[name]}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import modbfft as mb
+        import oracle
+        nn = (96, 96, 96)
+        p96 = geo.phase_map(nn, S, geo.PV).cpu().numpy()
+        tc = time.perf_counter()
+        ro = mb.solve(nn, p96, C1, E, tol=1e-30, maxit=5)
+        secs = time.perf_counter() - tc
+        cpu = {"value": int(np.prod(nn)) * ro["iterations"] / secs, "unit": "voxel-iterations/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"{ro['iterations']} preconditioned CG iterations of the MoDBFFT oracle (numpy FFTs, one "
+                         f"thread per transform) on the same octet at 96^3, {secs:.1f} s including the right-hand "
+                         f"side and the final fields"}
+        log(f"cpu baseline {cpu['value']:.3e} voxel-it/s")
+    cfg.update({"iterations": its, "rel_residual": out["rel_residual"], "wall_s": round(wall, 3),
+                "eff_stress": [float(v) for v in out["eff_stress"]], "alpha_used": out["alpha"],
+                "galerkin_same_map": gal, "parallelism": "single-gpu"})
+    line = {"metric": "MoDBFFT voxel-iterations/s and wall time to 1e-6 (octet PV 216^3)",
+            "value": nvox * its / wall, "unit": "voxel-iterations/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+            "ms_per_step": 1e3 * wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic", "config": cfg, "roofline": roof, "cpu_baseline": cpu,
+            "kernels": kernels}
+    print(json.dumps(line), flush=True)
+
+
 def bench_j2(args, n, cfg):
     """Nonlinear J2 ramp: wall time of the whole stress-strain curve (Newton + MINRES, FP32-mixed),
     MINRES voxel-iterations per second over it, per-kernel times of a profiled two-increment ramp,
@@ -389,13 +483,18 @@ def bench_j2(args, n, cfg):
     kw = dict(increments=cfg["increments"], newton_tol=cfg["newton_tol"], lin_tol=cfg["lin_tol"], stress_mask=0b111110,
               macro_stress_final=np.zeros(6), precision=prec, workspace=ws, max_iter=5000)
 
-    def ramp(**over):
+    def ramp(first=None, ph=None, **over):
+        """The ramp; first=k: only its first k increments (same increment size)."""
         k = dict(kw)
         k.update(over)
-        return rve.solve_j2(phi, m["young_MPa"], m["poisson"], m["yield_MPa"], E, **k)
+        Ek = E
+        if first:
+            Ek = [e * first / k["increments"] for e in E]
+            k["increments"] = first
+        return rve.solve_j2(phi if ph is None else ph, m["young_MPa"], m["poisson"], m["yield_MPa"], Ek, **k)
 
     for _ in range(args.warmup):
-        ramp(increments=2)
+        ramp(first=2)
     torch.cuda.synchronize()
     ts = time.perf_counter()
     out = ramp()
@@ -407,10 +506,29 @@ def bench_j2(args, n, cfg):
     value = nvox * minres / wall
     curve = [[round(float(h["strain_mean"][0]), 5), round(float(h["stress_mean"][0]), 4)] for h in hist]
     log(f"ramp {wall:.2f}s, newton {[h['newton'] for h in hist]}, minres {minres}, status {out['status']}")
-    # per-kernel: a profiled two-increment ramp (launches one at a time)
+    # the paper's other densities at about 15 voxels per diameter (untimed curves)
+    others = {}
+    for rho_o, n_o in ((0.2, 108), (0.3, 90)):
+        r_o = ds.target_radius(rho_o)
+        p_o = geo.phase_map(n_o, li.octet_struts(r_o), geo.VA, want_f32=True)
+        if not args.no_autotune:
+            rve.autotune((n_o,) * 3, n_cases=1, precision=prec)
+        to = time.perf_counter()
+        o = ramp(ph=p_o[1])
+        torch.cuda.synchronize()
+        others[str(rho_o)] = {"grid": n_o, "radius": r_o, "rho_actual": float(p_o[0].mean().item()),
+                              "voxels_per_diameter": round(2 * r_o * n_o, 2), "wall_s": round(time.perf_counter() - to, 3),
+                              "newton_per_increment": [h["newton"] for h in o["history"]],
+                              "minres_total": sum(h["minres"] for h in o["history"]), "status": o["status"],
+                              "stress_strain_curve": [[round(float(h["strain_mean"][0]), 5),
+                                                       round(float(h["stress_mean"][0]), 4)] for h in o["history"]]}
+        log(f"rho {rho_o}: {others[str(rho_o)]['wall_s']}s newton {others[str(rho_o)]['newton_per_increment']}")
+        del p_o
+    cfg["other_densities"] = others
+    # per-kernel: the first two increments again with every launch timed alone (no graphs)
     rve.profile_reset()
     rve.profile_enable(True)
-    ramp(increments=2)
+    ramp(first=2)
     torch.cuda.synchronize()
     rve.profile_enable(False)
     prof = rve.profile_read()
