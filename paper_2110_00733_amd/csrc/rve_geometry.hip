@@ -112,42 +112,121 @@ __device__ __forceinline__ void load_struts(const rve_strut* __restrict__ struts
   }
 }
 
+// Candidate struts of a set of rows along axis 2: only x_2 varies along a row, and the nearest-image
+// offsets to a strut midpoint in x_0 and x_1 are those of the row, so the distance of every point of
+// the row to the strut axis is at least the in-plane distance from (dx_0, dx_1) to the axis projected
+// onto the (x_0, x_1) plane.  A strut whose bound minus its radius exceeds `cut` (plus a margin far above
+// rounding) cannot decide an inside test (cut = 0) or lower a distance below cut (VA: cut = ell/2).
+// row(j, &x0, &x1) gives the rows' coordinates; all threads of the block call this (barriers inside).
+template <typename RowFn>
+__device__ int block_candidates(const StrutPrep* sp, int ns, const Cell& cell, int nrows, RowFn row, double cut,
+                                int* cand, int* wave_cnt) {
+#pragma clang fp contract(off)
+  bool keep = false;
+  const int k = threadIdx.x;
+  if (k < ns) {
+    const StrutPrep& q = sp[k];
+    const double h0 = q.half[0], h1 = q.half[1];
+    const double hh2 = h0 * h0 + h1 * h1;
+    const double margin = 1e-9 * (cell.L[0] + cell.L[1] + cell.L[2]);
+    for (int j = 0; j < nrows && !keep; ++j) {
+      double x0, x1;
+      row(j, &x0, &x1);
+      double d0 = x0 - q.mid[0], d1 = x1 - q.mid[1];
+      d0 -= cell.L[0] * floor(d0 / cell.L[0] + 0.5);
+      d1 -= cell.L[1] * floor(d1 / cell.L[1] + 0.5);
+      double t = hh2 > 0.0 ? (d0 * h0 + d1 * h1) / hh2 : 0.0;
+      t = t < -1.0 ? -1.0 : (t > 1.0 ? 1.0 : t);
+      const double e0 = d0 - t * h0, e1 = d1 - t * h1;
+      if (sqrt(e0 * e0 + e1 * e1) - q.r <= cut + margin) keep = true;
+    }
+  }
+  const unsigned long long bal = __ballot(keep);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) wave_cnt[wv] = __popcll(bal);
+  __syncthreads();
+  int off = 0, n = 0;
+  for (int u = 0; u < (int)(blockDim.x >> 6); ++u) {
+    if (u < wv) off += wave_cnt[u];
+    n += wave_cnt[u];
+  }
+  if (keep) cand[off + __popcll(bal & ((1ull << lane) - 1ull))] = k;
+  __syncthreads();
+  return n;
+}
+
 // ------------------------------------------------------------------ Voigt maps on the coarse grid
+// A block takes blockDim consecutive voxels at a time; their struts are culled over the rows (and, for
+// VFG, the sub-rows) they span, when those are few enough for the test to be cheap.
 __global__ __launch_bounds__(kThreads) void k_phase_map(const rve_strut* __restrict__ struts, int ns, Cell cell,
                                                         int n0, int n1, int n2, int kind, int sub, double ell,
                                                         double* __restrict__ phi, float* __restrict__ phi32) {
 #pragma clang fp contract(off)
   __shared__ StrutPrep sp[RVE_GEOMETRY_MAX_STRUTS];
+  __shared__ int cand[RVE_GEOMETRY_MAX_STRUTS];
+  __shared__ int wave_cnt[kThreads / 64];
   load_struts(struts, ns, cell.L, sp);
   __syncthreads();
   const long long nv = (long long)n0 * n1 * n2;
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (long long)gridDim.x * blockDim.x) {
-    const int i2 = (int)(v % n2);
-    const long long r = v / n2;
-    const int i1 = (int)(r % n1), i0 = (int)(r / n1);
-    double val;
-    if (kind == RVE_MAP_VFG) {
-      int cnt = 0;
-      for (int s0 = 0; s0 < sub; ++s0)
-        for (int s1 = 0; s1 < sub; ++s1)
-          for (int s2 = 0; s2 < sub; ++s2) {
-            const double x[3] = {((double)(i0 * sub + s0) + 0.5) * cell.h[0], ((double)(i1 * sub + s1) + 0.5) * cell.h[1],
-                                 ((double)(i2 * sub + s2) + 0.5) * cell.h[2]};
-            cnt += inside(sp, ns, cell.L, x) ? 1 : 0;
-          }
-      val = (double)cnt / (double)(sub * sub * sub);
-    } else {
-      const double x[3] = {((double)i0 + 0.5) * cell.h[0], ((double)i1 + 0.5) * cell.h[1], ((double)i2 + 0.5) * cell.h[2]};
-      if (kind == RVE_MAP_PV) {
-        val = inside(sp, ns, cell.L, x) ? 1.0 : 0.0;
-      } else {
-        const double D = signed_distance(sp, ns, cell.L, x);
-        val = 0.5 - D / ell;
-        val = val < 0.0 ? 0.0 : (val > 1.0 ? 1.0 : val);
-      }
+  const double cut = kind == RVE_MAP_VA ? 0.5 * ell : 0.0;
+  const int sub2 = sub * sub;
+  for (long long v0 = (long long)blockIdx.x * blockDim.x; v0 < nv; v0 += (long long)gridDim.x * blockDim.x) {
+    const long long ra = v0 / n2, rb = std::min(nv - 1, v0 + (long long)blockDim.x - 1) / n2;
+    const long long nrows = (rb - ra + 1) * sub2;
+    int nc = ns;
+    const int* list = nullptr;
+    if (nrows <= 1024) {
+      nc = block_candidates(sp, ns, cell, (int)nrows,
+                            [&](int j, double* x0, double* x1) {
+                              const long long r = ra + j / sub2;
+                              const int s = j % sub2;
+                              const int i1 = (int)(r % n1), i0 = (int)(r / n1);
+                              *x0 = ((double)(i0 * sub + s / sub) + 0.5) * cell.h[0];
+                              *x1 = ((double)(i1 * sub + s % sub) + 0.5) * cell.h[1];
+                            },
+                            cut, cand, wave_cnt);
+      list = cand;
     }
-    if (phi) phi[v] = val;
-    if (phi32) phi32[v] = (float)val;
+    const long long v = v0 + threadIdx.x;
+    if (v < nv) {
+      const int i2 = (int)(v % n2);
+      const long long r = v / n2;
+      const int i1 = (int)(r % n1), i0 = (int)(r / n1);
+      auto strut = [&](int c) -> const StrutPrep& { return sp[list ? list[c] : c]; };
+      auto is_in = [&](const double x[3]) {
+        for (int c = 0; c < nc; ++c)
+          if (axis_distance(strut(c), cell.L, x) - strut(c).r <= 0.0) return true;
+        return false;
+      };
+      double val;
+      if (kind == RVE_MAP_VFG) {
+        int cnt = 0;
+        for (int s0 = 0; s0 < sub; ++s0)
+          for (int s1 = 0; s1 < sub; ++s1)
+            for (int s2 = 0; s2 < sub; ++s2) {
+              const double x[3] = {((double)(i0 * sub + s0) + 0.5) * cell.h[0], ((double)(i1 * sub + s1) + 0.5) * cell.h[1],
+                                   ((double)(i2 * sub + s2) + 0.5) * cell.h[2]};
+              cnt += is_in(x) ? 1 : 0;
+            }
+        val = (double)cnt / (double)(sub * sub * sub);
+      } else {
+        const double x[3] = {((double)i0 + 0.5) * cell.h[0], ((double)i1 + 0.5) * cell.h[1], ((double)i2 + 0.5) * cell.h[2]};
+        if (kind == RVE_MAP_PV) {
+          val = is_in(x) ? 1.0 : 0.0;
+        } else {
+          double D = INFINITY;
+          for (int c = 0; c < nc; ++c) {
+            const double d = axis_distance(strut(c), cell.L, x) - strut(c).r;
+            if (d < D) D = d;
+          }
+          val = 0.5 - D / ell;
+          val = val < 0.0 ? 0.0 : (val > 1.0 ? 1.0 : val);
+        }
+      }
+      if (phi) phi[v] = val;
+      if (phi32) phi32[v] = (float)val;
+    }
+    __syncthreads();  // the candidate list is rebuilt for the next chunk
   }
 }
 
