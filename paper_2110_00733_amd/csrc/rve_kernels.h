@@ -438,6 +438,66 @@ __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, cx<T>* 
   }
 }
 
+// ============================================================================ strided axes
+// Complex FFT along a strided axis of [ncomp][n0][n1][K] arrays (the displacement solver's half
+// spectra, K = n2/2 + 1 contiguous), in place, component blockIdx.z (cstride elements apart): axis 1
+// (pencils of n1 elements K apart, blockIdx.y = n0) or axis 0 (pencils of n0 elements n1*K apart).
+// A block takes R pencils that are adjacent in memory, with the pencil index fastest across lanes, so
+// that every load and store instruction covers runs of R consecutive complex values; the transform is
+// the same two register stages with one LDS exchange as the Galerkin passes.  S < 0 forward, S > 0
+// inverse (unnormalised).  grid (ceil(pencils/R), n0 or 1, ncomp), block R*NB threads, dyn. LDS
+// R*(NA*(NB+1)+1) complex.
+template <typename T, int NA, int NB, int S>
+__global__ __launch_bounds__(256) void k_strided(cx<T>* __restrict__ data, long long cstride, int n1, int K, int axis,
+                                                 const cx<T>* __restrict__ tw, int R) {
+  constexpr int N = NA * NB;
+  constexpr int TT = NB;
+  constexpr int CB = (NA + TT - 1) / TT;
+  constexpr int RSW = NA * (NB + 1) + 1;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int w = tid % R, t = tid / R;
+  long long base, es;
+  int valid;
+  if (axis == 1) {
+    const int k0 = blockIdx.x * R;
+    base = (long long)blockIdx.y * n1 * K + k0;
+    es = K;
+    valid = min(R, K - k0);
+  } else {
+    const long long q0 = (long long)blockIdx.x * R;
+    es = (long long)n1 * K;
+    base = q0;
+    valid = (int)min((long long)R, es - q0);
+  }
+  const bool ok = w < valid;
+  cx<T>* d = data + (long long)blockIdx.z * cstride + base + w;
+  cx<T> z[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) z[i] = ok ? d[(long long)(t + NB * i) * es] : mk<T>(0, 0);
+  DFT<NA, S, T>::run(z);
+#pragma unroll
+  for (int a = 1; a < NA; ++a) z[a] = (S < 0) ? cmul(z[a], tw[(t * a) % N]) : cmulc(z[a], tw[(t * a) % N]);
+#pragma unroll
+  for (int a = 0; a < NA; ++a) lds[w * RSW + a * (NB + 1) + t] = z[a];
+  lds_barrier();
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int a = t + TT * j;
+    if (a < NA) {
+      cx<T> yb[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) yb[u] = lds[w * RSW + a * (NB + 1) + u];
+      DFT<NB, S, T>::run(yb);
+      if (ok) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) d[(long long)(a + NA * b) * es] = yb[b];
+      }
+    }
+  }
+}
+
 // ============================================================================ P3
 // Galerkin projection of one frequency (eq. galop): Ghat S = t (x) n + n (x) t - (n.t) n (x) n with
 // n = w/|w| and t = S n, applied to the Mandel components (S0..S5) in place and scaled by f (the 1/N

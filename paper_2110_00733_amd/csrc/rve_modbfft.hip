@@ -5,7 +5,7 @@
 // Half spectra are [c][n0][n1][K] FP64 complex (K = n2/2 + 1, k2 contiguous), S = n0 n1 K elements per
 // component.  One application of K:
 //   expand      u_hat (3) -> eps_hat (6, Mandel) and g_hat = -i alpha xi . eps_hat (3)     pointwise
-//   ifft axis 0, ifft axis 1 of the 9 components                                   k_strided_c2c
+//   ifft axis 0, ifft axis 1 of the 9 components                      k_strided / k_strided_c2c
 //   axis 2      per row: complex-to-real inverse of the 9 components (two per complex transform),
 //               1/N, sigma = phi C_m eps, h = (1 - phi) g, forward real-to-complex    k_row_stress
 //   fft axis 1, fft axis 0 of the 9 components
@@ -25,6 +25,7 @@
 #include "rve.h"
 #include "rve_lds_fft.h"
 #include "rve_modbfft.h"
+#include "rve_registry.h"
 
 namespace rve {
 void set_last_error(const char* text);
@@ -38,6 +39,19 @@ constexpr int kBlocks = 2048;  // blocks of the pointwise kernels (and their par
 constexpr double kSqrt2 = 1.41421356237309504880;
 constexpr int kMaxRow = 768;   // longest axis 2 (five complex rows of it in a 64 KiB tile)
 constexpr int kRowSlots = (kMaxRow + kThreads - 1) / kThreads;
+
+// pencils per block of the register-stage strided transforms: whole waves where possible, at most
+// 256 threads and 64 KiB of LDS, no more than the pencils there are
+static int register_pencils(int na, int nb, long long pencils) {
+  const long long per = (long long)(na * (nb + 1) + 1) * (long long)sizeof(C);
+  int any = 1, full = 0;
+  for (int r = 1; r <= 64 && r * nb <= 256 && r * per <= 65536; ++r) {
+    any = r;
+    if ((r * nb) % 64 == 0) full = r;
+  }
+  const int r = full ? full : any;
+  return (int)std::max<long long>(1, std::min<long long>(r, pencils));
+}
 
 struct MGrid {
   int n0, n1, n2, K;
@@ -668,7 +682,29 @@ rve_status solve_rve_modbfft(const rve_grid* grid, const float* phi, const doubl
   const dim3 gr1((unsigned)((g.K + TW1 - 1) / TW1), (unsigned)g.n0, 1);
   const size_t lds0 = (size_t)TW0 * g.n0 * sizeof(C), lds1 = (size_t)TW1 * g.n1 * sizeof(C);
   const unsigned rows = (unsigned)((long long)g.n0 * g.n1);
+  // lengths with a compiled factorisation take the register-stage kernels, the others the LDS plan
+  const rve::LenEntry* reg[2] = {rve::lookup_len(g.n0), rve::lookup_len(g.n1)};
+  int RP[2] = {0, 0};
+  dim3 grr[2];
+  size_t ldsr[2] = {0, 0};
+  for (int p = 0; p < 2; ++p) {
+    if (!reg[p]) continue;
+    const long long pencils = p == 0 ? (long long)g.n1 * g.K : g.K;
+    RP[p] = register_pencils(reg[p]->na, reg[p]->nb, pencils);
+    grr[p] = dim3((unsigned)((pencils + RP[p] - 1) / RP[p]), p == 0 ? 1u : (unsigned)g.n0, 1);
+    ldsr[p] = (size_t)RP[p] * (reg[p]->na * (reg[p]->nb + 1) + 1) * sizeof(C);
+  }
   auto strided = [&](int pass, int sign, int axis, int ncomp) {
+    if (reg[axis]) {
+      dim3 gr = grr[axis];
+      gr.z = ncomp;
+      const rve::LenKernels<double>& k = reg[axis]->d;
+      T.begin(pass);
+      hipLaunchKernelGGL(sign < 0 ? k.scf : k.sci, gr, dim3(RP[axis] * reg[axis]->nb), ldsr[axis], s, W, g.S, g.n1,
+                         g.K, axis, tw[axis], RP[axis]);
+      T.end();
+      return;
+    }
     dim3 gr = axis == 0 ? gr0 : gr1;
     gr.z = ncomp;
     T.begin(pass);

@@ -16,6 +16,9 @@ using P5Fn = void (*)(const cx<T>*, T*, const T*, const T*, double*, const cx<T>
                       const MinresState*);
 
 template <typename T>
+using SCFn = void (*)(cx<T>*, long long, int, int, int, const cx<T>*, int);
+
+template <typename T>
 struct LenKernels {
   P1Fn<T> p1, p1t;  // p1t: with the per-voxel elastic-plastic tangent (Material::tan)
   P2Fn<T> p2f, p2i;
@@ -23,6 +26,7 @@ struct LenKernels {
   P3Fn<T> p3s, p3s_ident;  // components split over two halves of the block
   P3Fn<T> p3t, p3t_ident;  // components split over three groups of the block
   P5Fn<T> p5;
+  SCFn<T> scf, sci;  // forward / inverse transforms along a strided axis (k_strided)
 };
 
 struct LenEntry {
@@ -39,6 +43,8 @@ inline const LenKernels<double>& LenEntry::k<double>() const { return d; }
 
 void register_len(const LenEntry& e);
 const LenEntry* find_len(int n, int variant = 0);
+// the default factorisation of a length (the table is filled on first use), or nullptr
+const LenEntry* lookup_len(int n);
 
 }  // namespace rve
 
@@ -47,6 +53,6 @@ const LenEntry* find_len(int n, int variant = 0);
    &rve::k_axis0_project<T_, NA_, NB_, false>, &rve::k_axis0_project<T_, NA_, NB_, true>,              \
    &rve::k_axis0_project_split<T_, NA_, NB_, false>, &rve::k_axis0_project_split<T_, NA_, NB_, true>,  \
    &rve::k_axis0_project_split3<T_, NA_, NB_, false>, &rve::k_axis0_project_split3<T_, NA_, NB_, true>, \
-   &rve::k_inv_axis2<T_, NA_, NB_>}
+   &rve::k_inv_axis2<T_, NA_, NB_>, &rve::k_strided<T_, NA_, NB_, -1>, &rve::k_strided<T_, NA_, NB_, 1>}
 #define RVE_LEN_ENTRY(N_, NA_, NB_) \
   rve::LenEntry { N_, NA_, NB_, RVE_LEN_KERNELS(float, NA_, NB_), RVE_LEN_KERNELS(double, NA_, NB_) }

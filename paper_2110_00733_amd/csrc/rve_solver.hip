@@ -68,6 +68,10 @@ static void ensure_registry() {
     if (f && f[0]) rve_load_tuning(f);
   });
 }
+const LenEntry* lookup_len(int n) {
+  ensure_registry();
+  return find_len(n, 0);
+}
 
 // ============================================================================ per-kernel timing
 // Optional HIP-event timing of every launch inside the MINRES iteration loop (on the solve stream).
