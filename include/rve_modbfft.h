@@ -15,11 +15,11 @@
  * equation times -1; chi = 1 - phi (the void indicator for plain voxels); alpha = 1e-4 E of the solid
  * by default.  Every step is FP64.
  *
- * One operator application is six streaming passes over nine components (the six Mandel strain
- * components and the three components of -div(alpha eps)): expand u_hat -> (eps_hat, g_hat); inverse
- * FFT along axis 0, axis 1; along axis 2 the inverse (complex-to-real), the pointwise
- * sigma = phi C_m eps and h = (1 - phi) g, and the forward transform in one pass; forward FFT along
- * axis 1, axis 0; then K_hat = -i xi . sigma_hat + h_hat (contract).  Lengths: 5-smooth, at most 1024
+ * One operator application is six streaming passes over nine components (the six Mandel components
+ * of the solid's stress s = C_m eps and the three of g = -div(alpha eps)): expand u_hat -> (s_hat,
+ * g_hat); inverse FFT along axis 0, axis 1; along axis 2 the inverse (complex-to-real), the pointwise
+ * sigma = phi s and h = (1 - phi) g, and the forward transform in one pass; forward FFT along axis 1,
+ * axis 0; then K_hat = -i xi . sigma_hat + h_hat (contract).  Lengths: 5-smooth, at most 1024
  * per axis and 768 along axis 2.
  * Conventions of rve.h: fields [6][n0][n1][n2] (Mandel), device/host as marked, the caller owns every
  * buffer, host validation before any device work, the stream is synchronised before returning.

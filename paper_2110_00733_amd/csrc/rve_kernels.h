@@ -498,6 +498,126 @@ __global__ __launch_bounds__(256) void k_strided(cx<T>* __restrict__ data, long 
   }
 }
 
+// Rows along axis 2 of the same arrays: per component pair (2 q, 2 q + 1; blockIdx.z = q, the second
+// absent when 2 q + 1 = ncomp) the complex-to-real inverse of the two half spectra packed as one
+// complex transform, the real fields times scale * phi(x) (components below nphi, an even count) or
+// scale * (1 - phi(x)), and the real-to-complex forward transform back in place.  A block takes W
+// consecutive rows (contiguous in every component, NB threads per row); per row one LDS area holds in
+// turn the Hermitian-extended sequence, the exchange between the register stages and the natural-order
+// result.  grid (ceil(rows/W), 1, ceil(ncomp/2)), block W*NB threads, dyn. LDS W*max(N+1, NA*(NB+1))
+// complex.
+template <typename T, int NA, int NB>
+__global__ __launch_bounds__(256) void k_row_pair(cx<T>* __restrict__ data, long long cstride,
+                                                  const float* __restrict__ phi, long long rows, int K, int ncomp,
+                                                  int nphi, T scale, const cx<T>* __restrict__ tw, int W) {
+  constexpr int N = NA * NB;
+  constexpr int TT = NB;
+  constexpr int CB = (NA + TT - 1) / TT;
+  constexpr int RS = (N + 1 > NA * (NB + 1)) ? N + 1 : NA * (NB + 1);
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int q = blockIdx.z;
+  const bool has1 = 2 * q + 1 < ncomp;
+  const bool by_phi = 2 * q < nphi;
+  const int tid = threadIdx.x;
+  const int t = tid % TT, w = tid / TT;
+  const long long r0 = (long long)blockIdx.x * W;
+  const int nrow = (int)min((long long)W, rows - r0);
+  const bool row_ok = w < nrow;
+  cx<T>* A = data + (long long)(2 * q) * cstride + r0 * K;
+  cx<T>* B = data + (long long)(has1 ? 2 * q + 1 : 2 * q) * cstride + r0 * K;
+  cx<T>* L = lds + w * RS;
+  // the pair's half spectra -> a + i b on the full circle (a real row's DC and Nyquist terms are real)
+  for (int idx = tid; idx < nrow * K; idx += blockDim.x) {
+    const int ww = idx / K, k = idx - ww * K;
+    const cx<T> a = A[idx];
+    const cx<T> b = has1 ? B[idx] : mk<T>(0, 0);
+    cx<T>* sq = lds + ww * RS;
+    if (k == 0 || 2 * k == N) {
+      sq[k] = mk<T>(a.re, b.re);
+    } else {
+      sq[k] = mk<T>(a.re - b.im, a.im + b.re);
+      sq[N - k] = mk<T>(a.re + b.im, b.re - a.im);
+    }
+  }
+  lds_barrier();
+  cx<T> z[NA];
+  cx<T> yb[CB][NB];
+  // inverse transform: register stage A, exchange, register stage B
+#pragma unroll
+  for (int i = 0; i < NA; ++i) z[i] = L[t + NB * i];
+  DFT<NA, 1, T>::run(z);
+#pragma unroll
+  for (int a = 1; a < NA; ++a) z[a] = cmulc(z[a], tw[(t * a) % N]);
+  lds_barrier();
+#pragma unroll
+  for (int a = 0; a < NA; ++a) L[a * (NB + 1) + t] = z[a];
+  lds_barrier();
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int a = t + TT * j;
+    if (a < NA) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) yb[j][u] = L[a * (NB + 1) + u];
+      DFT<NB, 1, T>::run(yb[j]);
+    }
+  }
+  lds_barrier();
+  // the two real fields times the phase factor, in natural order
+  const float* ph = phi + (r0 + (row_ok ? w : 0)) * (long long)N;
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int a = t + TT * j;
+    if (a < NA) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int e = a + NA * b;
+        const T m = row_ok ? (T)ph[e] : (T)0;
+        const T f = (by_phi ? m : (T)1 - m) * scale;
+        L[e] = mk<T>(yb[j][b].re * f, yb[j][b].im * f);
+      }
+    }
+  }
+  lds_barrier();
+  // forward transform
+#pragma unroll
+  for (int i = 0; i < NA; ++i) z[i] = L[t + NB * i];
+  DFT<NA, -1, T>::run(z);
+#pragma unroll
+  for (int a = 1; a < NA; ++a) z[a] = cmul(z[a], tw[(t * a) % N]);
+  lds_barrier();
+#pragma unroll
+  for (int a = 0; a < NA; ++a) L[a * (NB + 1) + t] = z[a];
+  lds_barrier();
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int a = t + TT * j;
+    if (a < NA) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) yb[j][u] = L[a * (NB + 1) + u];
+      DFT<NB, -1, T>::run(yb[j]);
+    }
+  }
+  lds_barrier();
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int a = t + TT * j;
+    if (a < NA) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) L[a + NA * b] = yb[j][b];
+    }
+  }
+  lds_barrier();
+  // separate the two half spectra
+  for (int idx = tid; idx < nrow * K; idx += blockDim.x) {
+    const int ww = idx / K, k = idx - ww * K;
+    const cx<T>* sq = lds + ww * RS;
+    const cx<T> Z = sq[k], Zm = sq[(N - k) % N];
+    A[idx] = mk<T>((Z.re + Zm.re) * (T)0.5, (Z.im - Zm.im) * (T)0.5);
+    if (has1) B[idx] = mk<T>((Z.im + Zm.im) * (T)0.5, (Zm.re - Z.re) * (T)0.5);
+  }
+}
+
 // ============================================================================ P3
 // Galerkin projection of one frequency (eq. galop): Ghat S = t (x) n + n (x) t - (n.t) n (x) n with
 // n = w/|w| and t = S n, applied to the Mandel components (S0..S5) in place and scaled by f (the 1/N

@@ -4,10 +4,11 @@
 //
 // Half spectra are [c][n0][n1][K] FP64 complex (K = n2/2 + 1, k2 contiguous), S = n0 n1 K elements per
 // component.  One application of K:
-//   expand      u_hat (3) -> eps_hat (6, Mandel) and g_hat = -i alpha xi . eps_hat (3)     pointwise
+//   expand      u_hat (3) -> s_hat = C_m eps_hat (6, Mandel; C_m is uniform) and
+//               g_hat = -i alpha xi . eps_hat (3)                                      pointwise
 //   ifft axis 0, ifft axis 1 of the 9 components                      k_strided / k_strided_c2c
-//   axis 2      per row: complex-to-real inverse of the 9 components (two per complex transform),
-//               1/N, sigma = phi C_m eps, h = (1 - phi) g, forward real-to-complex    k_row_stress
+//   axis 2      per row and component pair (one complex transform): complex-to-real inverse,
+//               sigma = phi s / N or h = (1 - phi) g / N, forward real-to-complex k_row_pair / k_row_stress
 //   fft axis 1, fft axis 0 of the 9 components
 //   contract    K_hat = -i xi . sigma_hat + h_hat, zero at the modes with xi = 0, and the CG partial
 //               of <p, K p>                                                            k_contract
@@ -41,7 +42,9 @@ constexpr int kMaxRow = 768;   // longest axis 2 (five complex rows of it in a 6
 constexpr int kRowSlots = (kMaxRow + kThreads - 1) / kThreads;
 
 // pencils per block of the register-stage strided transforms: whole waves where possible, at most
-// 256 threads and 64 KiB of LDS, no more than the pencils there are
+// 256 threads and 64 KiB of LDS, no more than the pencils there are (runs of R adjacent pencils keep
+// the loads and stores coalesced; one-wave blocks of 5 pencils at 216 = 18 * 12 took 0.53 ms per
+// pass against 0.37-0.42 ms with 16)
 static int register_pencils(int na, int nb, long long pencils) {
   const long long per = (long long)(na * (nb + 1) + 1) * (long long)sizeof(C);
   int any = 1, full = 0;
@@ -106,10 +109,18 @@ __device__ double block_reduce(double v, double* sh) {
   return s;
 }
 
+struct Stiff {
+  double Cm[36];   // Mandel stiffness of the solid
+  double E[6];     // macroscopic strain (Mandel)
+};
+
 // ------------------------------------------------------------------ expand
-// W[0..6) = eps_hat (Mandel) = Mandel of (i/2)(xi_i u_j + xi_j u_i); W[6..9) = g_hat = -i alpha xi_j eps_hat_ij
-// (when ncomp == 9)
-__global__ __launch_bounds__(kThreads) void k_expand(const C* __restrict__ u, C* __restrict__ W, MGrid g, int ncomp) {
+// eps_hat = Mandel of (i/2)(xi_i u_j + xi_j u_i).  ncomp == 6: W[0..6) = eps_hat (for the fields).
+// ncomp == 9 (the operator): W[0..6) = s_hat = C_m eps_hat, the solid's stress of the strain, formed in
+// Fourier space since C_m is uniform (sigma = phi s is then a product per component in real space), and
+// W[6..9) = g_hat = -i alpha xi_j eps_hat_ij.
+__global__ __launch_bounds__(kThreads) void k_expand(const C* __restrict__ u, C* __restrict__ W, MGrid g, Stiff st,
+                                                     int ncomp) {
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < g.S; e += (long long)gridDim.x * blockDim.x) {
     double xi[3];
     if (!freq_of(g, e, xi, nullptr)) {
@@ -124,8 +135,21 @@ __global__ __launch_bounds__(kThreads) void k_expand(const C* __restrict__ u, C*
 #pragma unroll
       for (int j = 0; j < 3; ++j)
         et[i][j] = mul_i(scale(add(scale(uv[j], xi[i]), scale(uv[i], xi[j])), 0.5));
+    C em[6];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) W[a * g.S + e] = scale(et[kMi(a)][kMj(a)], a < 3 ? 1.0 : kSqrt2);
+    for (int a = 0; a < 6; ++a) em[a] = scale(et[kMi(a)][kMj(a)], a < 3 ? 1.0 : kSqrt2);
+    if (ncomp == 9) {
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        C sa = mk<double>(0.0, 0.0);
+#pragma unroll
+        for (int b = 0; b < 6; ++b) sa = add(sa, scale(em[b], st.Cm[6 * a + b]));
+        W[a * g.S + e] = sa;
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 6; ++a) W[a * g.S + e] = em[a];
+    }
     if (ncomp == 9) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -139,12 +163,8 @@ __global__ __launch_bounds__(kThreads) void k_expand(const C* __restrict__ u, C*
 }
 
 // ------------------------------------------------------------------ axis 2: inverse, stress, forward
-struct Stiff {
-  double Cm[36];   // Mandel stiffness of the solid
-  double E[6];     // macroscopic strain (Mandel)
-};
-
-// mode 0 (operator): 9 components in, 9 out.  mode 1 (right-hand side): sigma = phi C_m Ebar, 6 out.
+// mode 0 (operator): 9 components in (s = C_m eps and g), sigma = phi s and h = (1 - phi) g out.
+// mode 1 (right-hand side): sigma = phi C_m Ebar, 6 out.
 // mode 2 (fields): 6 components in, strain = Ebar + eps and stress = phi C_m strain written as real
 // fields, per-block partial sums of the stress components.  One row (i0, i1) per block.
 __global__ __launch_bounds__(kThreads) void k_row_stress(C* __restrict__ W, const float* __restrict__ phi, MGrid g,
@@ -201,8 +221,12 @@ __global__ __launch_bounds__(kThreads) void k_row_stress(C* __restrict__ W, cons
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
         double s = 0.0;
+        if (mode == 0) {
+          s = c[a];
+        } else {
 #pragma unroll
-        for (int b = 0; b < 6; ++b) s += st.Cm[6 * a + b] * eps[b];
+          for (int b = 0; b < 6; ++b) s += st.Cm[6 * a + b] * eps[b];
+        }
         sig[a] = ph * s;
       }
       if (mode == 2) {
@@ -694,6 +718,28 @@ rve_status solve_rve_modbfft(const rve_grid* grid, const float* phi, const doubl
     grr[p] = dim3((unsigned)((pencils + RP[p] - 1) / RP[p]), p == 0 ? 1u : (unsigned)g.n0, 1);
     ldsr[p] = (size_t)RP[p] * (reg[p]->na * (reg[p]->nb + 1) + 1) * sizeof(C);
   }
+  // the operator's row pass: per component pair with register stages where the length is compiled
+  const rve::LenEntry* reg2 = rve::lookup_len(g.n2);
+  int RW = 0;
+  size_t ldsw = 0;
+  if (reg2) {
+    // one wave per block (64 / NB rows): its barriers are cheap, and eight such blocks fit a CU's LDS
+    // at 216 = 18 * 12 (0.66 ms per pass there, against 0.79 ms with 16 rows of 192 threads); the rows
+    // are contiguous in every component, so the loads stay coalesced at any row count
+    const int rs = std::max(g.n2 + 1, reg2->na * (reg2->nb + 1));
+    RW = (int)std::max<long long>(1, std::min<long long>(std::max(1, 64 / reg2->nb), rows));
+    ldsw = (size_t)RW * rs * sizeof(C);
+  }
+  auto row_pass = [&]() {
+    T.begin(RVE_MODBFFT_AXIS2_STRESS);
+    if (reg2)
+      hipLaunchKernelGGL(reg2->d.rowp, dim3((unsigned)((rows + RW - 1) / RW), 1, 5), dim3(RW * reg2->nb), ldsw, s, W,
+                         g.S, phi, (long long)rows, g.K, 9, 6, 1.0 / (double)g.nvox, tw[2], RW);
+    else
+      hipLaunchKernelGGL(k_row_stress, dim3(rows), dim3(kThreads), lds_row9, s, W, phi, g, st, 0, P[2], tw[2], rev[2],
+                         (double*)nullptr, (double*)nullptr, part);
+    T.end();
+  };
   auto strided = [&](int pass, int sign, int axis, int ncomp) {
     if (reg[axis]) {
       dim3 gr = grr[axis];
@@ -755,14 +801,11 @@ rve_status solve_rve_modbfft(const rve_grid* grid, const float* phi, const doubl
     }
     // q = K p
     T.begin(RVE_MODBFFT_EXPAND);
-    hipLaunchKernelGGL(k_expand, dim3(kBlocks), dim3(kThreads), 0, s, (const C*)pv, W, g, 9);
+    hipLaunchKernelGGL(k_expand, dim3(kBlocks), dim3(kThreads), 0, s, (const C*)pv, W, g, st, 9);
     T.end();
     strided(RVE_MODBFFT_IFFT_AXIS0, 1, 0, 9);
     strided(RVE_MODBFFT_IFFT_AXIS1, 1, 1, 9);
-    T.begin(RVE_MODBFFT_AXIS2_STRESS);
-    hipLaunchKernelGGL(k_row_stress, dim3(rows), dim3(kThreads), lds_row9, s, W, phi, g, st, 0, P[2], tw[2], rev[2],
-                       (double*)nullptr, (double*)nullptr, part);
-    T.end();
+    row_pass();
     strided(RVE_MODBFFT_FFT_AXIS1, -1, 1, 9);
     strided(RVE_MODBFFT_FFT_AXIS0, -1, 0, 9);
     T.begin(RVE_MODBFFT_CONTRACT);
@@ -783,7 +826,7 @@ rve_status solve_rve_modbfft(const rve_grid* grid, const float* phi, const doubl
     if (T.on) T.collect(stats);
   }
   // fields and <sigma>
-  hipLaunchKernelGGL(k_expand, dim3(kBlocks), dim3(kThreads), 0, s, (const C*)x, W, g, 6);
+  hipLaunchKernelGGL(k_expand, dim3(kBlocks), dim3(kThreads), 0, s, (const C*)x, W, g, st, 6);
   strided(RVE_MODBFFT_IFFT_AXIS0, 1, 0, 6);
   strided(RVE_MODBFFT_IFFT_AXIS1, 1, 1, 6);
   hipLaunchKernelGGL(k_row_stress, dim3(rows), dim3(kThreads), lds_row6, s, W, phi, g, st, 2, P[2], tw[2], rev[2],

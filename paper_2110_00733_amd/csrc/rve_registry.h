@@ -19,6 +19,9 @@ template <typename T>
 using SCFn = void (*)(cx<T>*, long long, int, int, int, const cx<T>*, int);
 
 template <typename T>
+using RPFn = void (*)(cx<T>*, long long, const float*, long long, int, int, int, T, const cx<T>*, int);
+
+template <typename T>
 struct LenKernels {
   P1Fn<T> p1, p1t;  // p1t: with the per-voxel elastic-plastic tangent (Material::tan)
   P2Fn<T> p2f, p2i;
@@ -27,6 +30,7 @@ struct LenKernels {
   P3Fn<T> p3t, p3t_ident;  // components split over three groups of the block
   P5Fn<T> p5;
   SCFn<T> scf, sci;  // forward / inverse transforms along a strided axis (k_strided)
+  RPFn<T> rowp;      // per-pair row pass along axis 2 (k_row_pair)
 };
 
 struct LenEntry {
@@ -53,6 +57,7 @@ const LenEntry* lookup_len(int n);
    &rve::k_axis0_project<T_, NA_, NB_, false>, &rve::k_axis0_project<T_, NA_, NB_, true>,              \
    &rve::k_axis0_project_split<T_, NA_, NB_, false>, &rve::k_axis0_project_split<T_, NA_, NB_, true>,  \
    &rve::k_axis0_project_split3<T_, NA_, NB_, false>, &rve::k_axis0_project_split3<T_, NA_, NB_, true>, \
-   &rve::k_inv_axis2<T_, NA_, NB_>, &rve::k_strided<T_, NA_, NB_, -1>, &rve::k_strided<T_, NA_, NB_, 1>}
+   &rve::k_inv_axis2<T_, NA_, NB_>, &rve::k_strided<T_, NA_, NB_, -1>, &rve::k_strided<T_, NA_, NB_, 1>, \
+   &rve::k_row_pair<T_, NA_, NB_>}
 #define RVE_LEN_ENTRY(N_, NA_, NB_) \
   rve::LenEntry { N_, NA_, NB_, RVE_LEN_KERNELS(float, NA_, NB_), RVE_LEN_KERNELS(double, NA_, NB_) }

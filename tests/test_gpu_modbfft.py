@@ -35,9 +35,11 @@ CASES = [
     ((12, 10, 16), (1.0, 1.0, 1.0), 3, 0.2),
     ((9, 8, 15), (1.0, 1.2, 0.9), 4, 0.4),   # odd lengths, anisotropic cell
     ((16, 6, 20), (1.0, 1.0, 1.0), 5, 0.3),
-    # axes longer than the compiled register-stage lengths (256) take the LDS-plan transforms
+    # axes longer than the compiled register-stage lengths (256) take the LDS-plan transforms (the
+    # strided passes along axes 0 and 1, the row pass along axis 2)
     ((270, 3, 4), (2.7, 0.03, 0.04), 6, 0.2),
     ((4, 300, 6), (0.04, 3.0, 0.06), 7, 0.2),
+    ((3, 4, 270), (0.03, 0.04, 2.7), 8, 0.2),
 ]
 
 
