@@ -238,12 +238,23 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
 
   T sg[6][NA];
   {
+    // loads without a branch per element: a row past the grid's end reads the last row and its
+    // stresses are scaled by zero (a load under a per-lane condition made the compiler wait for the
+    // loads in flight before each address computation); the offsets NB * i are immediates on one base
+    // per field
+    const long long rowc = row_ok ? row : ((long long)n0 * g.n1 + (g.n1 - 1)) * N;
+    const T xso = row_ok ? xs : (T)0;
     T e[6][NA], ph[NA];
+    const float* pr = phic + rowc + t;
+    const T* xr[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) xr[c] = xc + (long long)c * g.nvox + rowc + t;
+    // element-major, so that the stiffness of element i can start once its seven values are in
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      ph[i] = (row_ok && mat.use_phi) ? (T)phic[row + t + NB * i] : (T)0;
+      ph[i] = mat.use_phi ? (T)pr[NB * i] : (T)0;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) e[c][i] = row_ok ? xc[c * g.nvox + row + t + NB * i] : (T)0;
+      for (int c = 0; c < 6; ++c) e[c][i] = xr[c][NB * i];
     }
     // element by element, so that e[.][i] is dead once sg[.][i] and its <x, sigma> terms exist
 #pragma unroll
@@ -254,15 +265,11 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
       const T tr = ev[0] + ev[1] + ev[2];
       if constexpr (TAN) {
         // C_t e = phi (Cd e - a dev(e) - (m . e) m), the tangent's data read element by element
-        const T* tp = mat.tan + (long long)cs * mat.tan_stride + row + t + NB * i;
-        T ta = 0, tm[6], md = 0;
+        const T* tp = mat.tan + (long long)cs * mat.tan_stride + rowc + t + NB * i;
+        T tm[6], md = 0;
+        const T ta = tp[0];
 #pragma unroll
-        for (int b = 0; b < 6; ++b) tm[b] = 0;
-        if (row_ok) {
-          ta = tp[0];
-#pragma unroll
-          for (int b = 0; b < 6; ++b) tm[b] = tp[(long long)(1 + b) * g.nvox];
-        }
+        for (int b = 0; b < 6; ++b) tm[b] = tp[(long long)(1 + b) * g.nvox];
 #pragma unroll
         for (int b = 0; b < 6; ++b) md += tm[b] * ev[b];
         const T tr3 = tr * (T)(1.0 / 3.0);
@@ -270,7 +277,7 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
         for (int a = 0; a < 6; ++a) {
           const T dv = a < 3 ? ev[a] - tr3 : ev[a];
           const T sv = stiff_row(mat.Cd, mat.iso_d, mat.lam_d, mat.mu2_d, a, ev, tr) - ta * dv - md * tm[a];
-          sg[a][i] = ph[i] * sv * xs;
+          sg[a][i] = ph[i] * sv * xso;
         }
       } else {
 #pragma unroll
@@ -278,7 +285,7 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
           T sv = 0;
           if (mat.use_phi) sv = ph[i] * stiff_row(mat.Cd, mat.iso_d, mat.lam_d, mat.mu2_d, a, ev, tr);
           if (mat.has_c0) sv += stiff_row(mat.C0, mat.iso_0, mat.lam_0, mat.mu2_0, a, ev, tr);
-          sg[a][i] = sv * xs;
+          sg[a][i] = sv * xso;
         }
       }
       if (partials) {
