@@ -479,10 +479,11 @@ __global__ __launch_bounds__(256) void k_strided(cx<T>* __restrict__ data, long 
     valid = (int)min((long long)R, es - q0);
   }
   const bool ok = w < valid;
-  cx<T>* d = data + (long long)blockIdx.z * cstride + base + w;
+  // a lane past the last pencil loads the last one (no per-lane condition on the loads) and stores nothing
+  cx<T>* d = data + (long long)blockIdx.z * cstride + base + (ok ? w : valid - 1);
   cx<T> z[NA];
 #pragma unroll
-  for (int i = 0; i < NA; ++i) z[i] = ok ? d[(long long)(t + NB * i) * es] : mk<T>(0, 0);
+  for (int i = 0; i < NA; ++i) z[i] = d[(long long)(t + NB * i) * es];
   DFT<NA, S, T>::run(z);
 #pragma unroll
   for (int a = 1; a < NA; ++a) z[a] = (S < 0) ? cmul(z[a], tw[(t * a) % N]) : cmulc(z[a], tw[(t * a) % N]);
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(256) void k_row_pair(cx<T>* __restrict__ data, long
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int e = a + NA * b;
-        const T m = row_ok ? (T)ph[e] : (T)0;
+        const T m = (T)ph[e];  // a row past the end reads row r0 and is not stored
         const T f = (by_phi ? m : (T)1 - m) * scale;
         L[e] = mk<T>(yb[j][b].re * f, yb[j][b].im * f);
       }
