@@ -402,14 +402,24 @@ __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, cx<T>* 
   // the tiled side addresses from the block's first plane with 32-bit offsets (the block's rows span
   // at most a few planes of n0*N1 <= 2^16 elements), so the loads and stores take a uniform base
   const cx<T>* tblk = spec_t + p0 * g.n0 * (long long)N;
-  const unsigned ta = oka ? (unsigned)((pa - p0) * g.n0 * N + spec_t_off(g, n0a, 0)) : 0u;
+  // loads without a per-lane condition (one made the compiler wait for the loads in flight): a row
+  // past the end reads the block's first row, a dead row (finished case) its own, and neither is
+  // stored; a wave with no live row loads nothing
+  const bool in_range = ra < total_rows;
+  const unsigned ta = in_range ? (unsigned)((pa - p0) * g.n0 * N + spec_t_off(g, n0a, 0)) : 0u;
+  const long long rac = in_range ? ra : row0;
   cx<T> z[NA];
-  if (S < 0) {
+  if (__ballot(oka) != 0) {
+    if (S < 0) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) z[i] = oka ? spec[ra * N + t1 + NB * i] : mk<T>(0, 0);
+      for (int i = 0; i < NA; ++i) z[i] = spec[rac * N + t1 + NB * i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) z[i] = tblk[ta + (unsigned)((t1 + NB * i) * g.tile)];
+    }
   } else {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) z[i] = oka ? tblk[ta + (unsigned)((t1 + NB * i) * g.tile)] : mk<T>(0, 0);
+    for (int i = 0; i < NA; ++i) z[i] = mk<T>(0, 0);
   }
   DFT<NA, S, T>::run(z);
 #pragma unroll
