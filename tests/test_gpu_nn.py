@@ -388,8 +388,9 @@ def test_warm_start_rejected_when_it_does_not_help():
 def test_trained_warm_start_on_heldout_lattice():
     """The committed network on a 64^3 defect lattice it never saw: its start is accepted with a much
     smaller initial residual than the zero start (about 0.15), the solve still converges to the same
-    effective stiffness, and the iteration count stays within a few percent of the zero start (the
-    remaining error sits in the slow surface-voxel modes)."""
+    effective stiffness, and the iteration count is at break-even with the zero start: measured 6146
+    against 6208 over the six cases (ratio 0.990; the remaining error sits in the slow surface-voxel
+    modes).  The bound allows 2% either way of that, not a gain the network does not give."""
     import torch
     import lattice_inputs as li
     import paper_2110_00733_amd as rve
@@ -413,4 +414,4 @@ def test_trained_warm_start_on_heldout_lattice():
     Cz, Cw = zero["eff_stress"], warm["eff_stress"]
     assert np.max(np.abs(Cz - Cw)) <= 2e-5 * np.max(np.abs(Cz))
     ratio = warm["iterations"].sum() / zero["iterations"].sum()
-    assert 0.8 < ratio < 1.1, ratio
+    assert 0.97 < ratio < 1.01, ratio
