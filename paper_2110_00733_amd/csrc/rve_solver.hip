@@ -1310,6 +1310,21 @@ static rve_status batch_iterate(std::vector<SolveRun>& runs, const std::vector<c
     HIPCHK(hipStreamSynchronize(s));
     prof::flush();
     int done_in_graph = 0;
+    // the solves whose sweeps ended are refined on the branch streams (idle between replays), so that
+    // their FP64 residual applies overlap; the next replay on s waits for all of them
+    const int nbs = (int)cache->branch.size();
+    int restarts = 0;
+    HIPCHK(hipEventRecord(cache->fork, s));
+    hipError_t wait_err = hipSuccess;
+    auto restart_stream = [&]() -> hipStream_t {
+      hipStream_t b = cache->branch[restarts % nbs];
+      if (restarts < nbs) {
+        const hipError_t e = hipStreamWaitEvent(b, cache->fork, 0);
+        if (e != hipSuccess) wait_err = e;
+      }
+      ++restarts;
+      return b;
+    };
     for (int r = 0; r < nr; ++r) {
       if (done[r]) {
         // still has nodes in the graph until the next capture
@@ -1330,16 +1345,22 @@ static rve_status batch_iterate(std::vector<SolveRun>& runs, const std::vector<c
           continue;
         }
       }
+      runs[r].s = restart_stream();
       st = runs[r].sweep_end();
-      if (st != RVE_OK) return st;
-      if (fp32 && sweeps[r] < opt->max_refine) {
+      if (st == RVE_OK && fp32 && sweeps[r] < opt->max_refine) {
         st = runs[r].sweep_begin(nullptr);  // its active flags are checked after the next replay
-        if (st != RVE_OK) return st;
         sweeps[r]++;
         pending_check[r] = 1;
       } else {
         done[r] = 1;  // counted among the graph's finished solves from the next replay on
       }
+      runs[r].s = s;
+      HIPCHK(wait_err);
+      if (st != RVE_OK) return st;
+    }
+    for (int b = 0; b < std::min(restarts, nbs); ++b) {
+      HIPCHK(hipEventRecord(cache->join[b], cache->branch[b]));
+      HIPCHK(hipStreamWaitEvent(s, cache->join[b], 0));
     }
     std::vector<SolveRun*> still;
     for (int r = 0; r < nr; ++r)
