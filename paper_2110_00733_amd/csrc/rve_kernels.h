@@ -796,7 +796,8 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
 // halving the registers per thread.  W*NB must be a multiple of the wave size (64) so that the half
 // index is uniform per wave and the half-dependent branches are scalar.
 // grid (ceil(N1/W), K2, ncases), block 2*W*NB threads, dyn. LDS
-// 2*NA*(NB*W+1) complex (one transform exchange area per half, reused for the projection exchange).
+// 2*NA*(NB*W+1) complex (one transform exchange area per half, reused for the projection exchange),
+// plus NA*NB complex in FP32 for a copy of the twiddle table.
 // For the projection, half h takes the entries e of parity h: in three rounds (one component
 // slot each) the halves swap the values of the entries the other half projects, so that a thread
 // holds all six components of its entries (own ones in D[r][e], the other half's in the slot D[r][e^1]
@@ -838,19 +839,19 @@ __global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__
 #pragma unroll
     for (int i = NA; i < E; ++i) D[c][i] = mk<T>(0, 0);
   }
-  // FP32: stage twiddles loaded once (the LDS barriers would force a reload per component); FP64
-  // reloads them from cache instead, its registers being full
-  constexpr bool HOIST = sizeof(T) == 4;
-  cx<T> twv[HOIST ? NA : 1];
-  if (HOIST) {
-#pragma unroll
-    for (int a = 1; a < NA; ++a) twv[HOIST ? a : 0] = tw[(t * a) % N];
+  // FP32: the twiddles are read from a copy in LDS (behind the two exchange areas), which keeps them
+  // out of the registers; FP64 reloads them from cache
+  constexpr bool TWL = sizeof(T) == 4;
+  cx<T>* twl = lds_all + 2 * NA * RS;
+  if (TWL) {
+    for (int i = tid; i < N; i += blockDim.x) twl[i] = tw[i];
+    __syncthreads();
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     DFT<NA, -1, T>::run(D[c]);
 #pragma unroll
-    for (int a = 1; a < NA; ++a) D[c][a] = cmul(D[c][a], HOIST ? twv[HOIST ? a : 0] : tw[(t * a) % N]);
+    for (int a = 1; a < NA; ++a) D[c][a] = cmul(D[c][a], TWL ? twl[(t * a) % N] : tw[(t * a) % N]);
     lds_barrier();
 #pragma unroll
     for (int a = 0; a < NA; ++a) lds[a * RS + w * NB + t] = D[c][a];
@@ -923,13 +924,6 @@ __global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__
   }
 
   // ---- inverse along axis 0
-  cx<T> twi[HOIST ? CB : 1][HOIST ? NB : 1];
-  if (HOIST) {
-#pragma unroll
-    for (int j = 0; j < CB; ++j)
-#pragma unroll
-      for (int u = 1; u < NB; ++u) twi[HOIST ? j : 0][HOIST ? u : 0] = tw[(u * (t + TT * j)) % N];
-  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
@@ -940,7 +934,7 @@ __global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__
         if (a > 0) {
 #pragma unroll
           for (int u = 1; u < NB; ++u)
-            D[c][j * NB + u] = cmulc(D[c][j * NB + u], HOIST ? twi[HOIST ? j : 0][HOIST ? u : 0] : tw[(u * a) % N]);
+            D[c][j * NB + u] = cmulc(D[c][j * NB + u], TWL ? twl[(u * a) % N] : tw[(u * a) % N]);
         }
       }
     }

@@ -219,7 +219,11 @@ static int tile_p3_for(const Plan& pl, int elem, int sp) {
   const int na = axis(pl, elem, 0)->na, nb = axis(pl, elem, 0)->nb;
   if (sp == 3) return 64 / nb;  // one wave per component group
   int W = pl.t[elem == 8].W3;
-  while (W > 1 && (W * nb > 256 || sp * 2LL * elem * na * (nb * W + 1) > pl.lds_cap3)) W /= 2;
+  // LDS of the split variants: the exchange areas, and in FP32 the twiddle table of the two-way split
+  auto lds_bytes = [&](int w) {
+    return sp * 2LL * elem * na * (nb * w + 1) + (sp == 2 && elem == 4 ? 2LL * elem * na * nb : 0);
+  };
+  while (W > 1 && (W * nb > 256 || lds_bytes(W) > pl.lds_cap3)) W /= 2;
   return W;
 }
 // LDS (complex elements) of the three-group P3 at tile W: the larger of its three transform exchange
@@ -509,7 +513,9 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
   {
     const int W = tile_p3(pl, elem);
     const int sp = split_p3(pl, elem);
-    const size_t lds = sizeof(cx<T>) * (sp == 3 ? lds_p3_split3(na0, nb0, W) : (long long)sp * na0 * (nb0 * W + 1));
+    const size_t lds = sizeof(cx<T>) * (sp == 3 ? lds_p3_split3(na0, nb0, W)
+                                                : (long long)sp * na0 * (nb0 * W + 1) +
+                                                      (sp == 2 && elem == 4 ? (long long)na0 * nb0 : 0));
     FreqTables<T> ft;
     for (int p = 0; p < 3; ++p) {
       ft.s[p] = tb.s[p];
