@@ -209,10 +209,19 @@ __device__ __forceinline__ void givens_step(MinresState& S, double sumsq) {
 }
 
 // ============================================================================ P1
-// grid (ceil(N1/W), N0, ncases), block W*NB threads, dyn. LDS W*max(NA*(NB+1), N+1) complex
+// grid (ceil(N1/W), N0, ncases), block W*NB threads, dyn. LDS W*max(NA*(NB+1), N+1) complex (+ N
+// complex in FP32 for the twiddle table)
 // With `partials` (MINRES iterations): per-block <x, sigma> partials for the Lanczos alpha.
+// Waves per SIMD P1 is compiled for: at 256 = 16 x 16 in FP32 (no tangent) it needs 130 VGPRs, two more
+// than four waves allow; capped there it runs four waves per SIMD.
+template <typename T, int NA, int NB, bool TAN>
+struct P1Waves {
+  static constexpr int value = (sizeof(T) == 4 && NA == 16 && NB == 16 && !TAN) ? 4 : 1;
+};
+
 template <typename T, int NA, int NB, bool TAN = false>
-__global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P1Waves<T, NA, NB, TAN>::value))) void
+k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib,
                                                    int xscale_stride, const float* __restrict__ phi, Material<T> mat,
                                                    cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, GridDims g,
                                                    int W, const MinresState* __restrict__ st, double* partials) {
@@ -223,6 +232,14 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int cs = blockIdx.z;
   if (st && st[cs].finish) return;
+  // FP32: the stage twiddles come from a copy of the table in LDS behind the exchange areas (read
+  // before the first transform, after a barrier), which keeps them out of the registers
+  constexpr bool TWL = sizeof(T) == 4;
+  constexpr int XA = (NA * (NB + 1) > N + 1) ? NA * (NB + 1) : N + 1;
+  cx<T>* twl = lds + W * XA;
+  if (TWL) {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = tw[i];
+  }
   const int n0 = blockIdx.y;
   const int n1_0 = blockIdx.x * W;
   const int tid = threadIdx.x;
@@ -296,12 +313,7 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
   }
   const int ws = tid % W, m = tid / W, M = blockDim.x / W;
   const int n1s = n1_0 + ws;
-  constexpr bool HOIST = sizeof(T) == 4;  // FP32: stage twiddles once, not once per component pair
-  cx<T> twv[HOIST ? NA : 1];
-  if (HOIST) {
-#pragma unroll
-    for (int a = 1; a < NA; ++a) twv[HOIST ? a : 0] = tw[(t * a) % N];
-  }
+  if (TWL) lds_barrier();
 #pragma unroll
   for (int pr = 0; pr < 3; ++pr) {
     cx<T> z[NA];
@@ -309,7 +321,7 @@ __global__ __launch_bounds__(256) void k_fwd_axis2(const T* __restrict__ x, cons
     for (int i = 0; i < NA; ++i) z[i] = mk<T>(sg[2 * pr][i], sg[2 * pr + 1][i]);
     DFT<NA, -1, T>::run(z);
 #pragma unroll
-    for (int a = 1; a < NA; ++a) z[a] = cmul(z[a], HOIST ? twv[HOIST ? a : 0] : tw[(t * a) % N]);
+    for (int a = 1; a < NA; ++a) z[a] = cmul(z[a], TWL ? twl[(t * a) % N] : tw[(t * a) % N]);
     lds_barrier();
 #pragma unroll
     for (int a = 0; a < NA; ++a) lds[(w * NA + a) * (NB + 1) + t] = z[a];

@@ -485,7 +485,7 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
   // P1
   {
     const int W = tile_p1(pl, elem);
-    const size_t lds = sizeof(cx<T>) * W * std::max(na2 * (nb2 + 1), N2 + 1);
+    const size_t lds = sizeof(cx<T>) * (W * std::max(na2 * (nb2 + 1), N2 + 1) + (elem == 4 ? N2 : 0));
     dim3 grid((g.n1 + W - 1) / W, g.n0, nc);
     prof::begin<T>(prof::P1, s);
     hipLaunchKernelGGL(mat.tan ? K2.p1t : K2.p1, grid, dim3(W * nb2), lds, s, x, xscale, (int)(sizeof(MinresState) / sizeof(double)),
@@ -1316,21 +1316,6 @@ static rve_status batch_iterate(std::vector<SolveRun>& runs, const std::vector<c
     HIPCHK(hipStreamSynchronize(s));
     prof::flush();
     int done_in_graph = 0;
-    // the solves whose sweeps ended are refined on the branch streams (idle between replays), so that
-    // their FP64 residual applies overlap; the next replay on s waits for all of them
-    const int nbs = (int)cache->branch.size();
-    int restarts = 0;
-    HIPCHK(hipEventRecord(cache->fork, s));
-    hipError_t wait_err = hipSuccess;
-    auto restart_stream = [&]() -> hipStream_t {
-      hipStream_t b = cache->branch[restarts % nbs];
-      if (restarts < nbs) {
-        const hipError_t e = hipStreamWaitEvent(b, cache->fork, 0);
-        if (e != hipSuccess) wait_err = e;
-      }
-      ++restarts;
-      return b;
-    };
     for (int r = 0; r < nr; ++r) {
       if (done[r]) {
         // still has nodes in the graph until the next capture
@@ -1351,22 +1336,16 @@ static rve_status batch_iterate(std::vector<SolveRun>& runs, const std::vector<c
           continue;
         }
       }
-      runs[r].s = restart_stream();
       st = runs[r].sweep_end();
-      if (st == RVE_OK && fp32 && sweeps[r] < opt->max_refine) {
+      if (st != RVE_OK) return st;
+      if (fp32 && sweeps[r] < opt->max_refine) {
         st = runs[r].sweep_begin(nullptr);  // its active flags are checked after the next replay
+        if (st != RVE_OK) return st;
         sweeps[r]++;
         pending_check[r] = 1;
       } else {
         done[r] = 1;  // counted among the graph's finished solves from the next replay on
       }
-      runs[r].s = s;
-      HIPCHK(wait_err);
-      if (st != RVE_OK) return st;
-    }
-    for (int b = 0; b < std::min(restarts, nbs); ++b) {
-      HIPCHK(hipEventRecord(cache->join[b], cache->branch[b]));
-      HIPCHK(hipStreamWaitEvent(s, cache->join[b], 0));
     }
     std::vector<SolveRun*> still;
     for (int r = 0; r < nr; ++r)
