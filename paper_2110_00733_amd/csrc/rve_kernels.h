@@ -366,8 +366,9 @@ k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib,
 
 // ============================================================================ P2 / P4
 // Rows of N1 complex, one per (case, k2, component, n0); grid (ceil(rows/R)), block R*NB threads,
-// dyn. LDS R*(NA*(NB+1)+1) complex.  P2 (S < 0) reads rows of spec and writes P3's tiled copy
-// (spec_t_off), P4 (S > 0) reads the tiled copy and writes rows of spec.  The side on spec runs with
+// dyn. LDS R*(NA*(NB+1)+1) complex (+ N complex in FP32 for the twiddle table).  P2 (S < 0) reads
+// rows of spec and writes P3's tiled copy (spec_t_off), P4 (S > 0) reads the tiled copy and writes
+// rows of spec.  The side on spec runs with
 // the element index fastest across lanes (adjacent along a row), the side on the tiled copy with the
 // row index fastest (consecutive n0 at one n1 are adjacent there); the LDS exchange between the two
 // transform stages hands the data from one lane order to the other.
@@ -382,6 +383,13 @@ __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, cx<T>* 
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x;
+  // FP32: the stage twiddles come from a copy of the table in LDS behind the rows' exchange areas,
+  // written first so that its loads do not wait behind the row loads
+  constexpr bool TWL = sizeof(T) == 4;
+  cx<T>* twl = lds + R * RSW;
+  if (TWL) {
+    for (int i = tid; i < N; i += blockDim.x) twl[i] = tw[i];
+  }
   const long long row0 = (long long)blockIdx.x * R;
   const int t_row = tid % TT, w_row = tid / TT;  // element index fastest
   const int w_til = tid % R, t_til = tid / R;    // row index fastest
@@ -434,8 +442,10 @@ __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, cx<T>* 
     for (int i = 0; i < NA; ++i) z[i] = mk<T>(0, 0);
   }
   DFT<NA, S, T>::run(z);
+  if (TWL) lds_barrier();  // the twiddle table is in place
+  const cx<T>* tws = TWL ? twl : tw;
 #pragma unroll
-  for (int a = 1; a < NA; ++a) z[a] = (S < 0) ? cmul(z[a], tw[(t1 * a) % N]) : cmulc(z[a], tw[(t1 * a) % N]);
+  for (int a = 1; a < NA; ++a) z[a] = (S < 0) ? cmul(z[a], tws[(t1 * a) % N]) : cmulc(z[a], tws[(t1 * a) % N]);
 #pragma unroll
   for (int a = 0; a < NA; ++a) lds[w1 * RSW + a * (NB + 1) + t1] = z[a];
   lds_barrier();

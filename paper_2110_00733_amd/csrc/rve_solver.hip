@@ -502,7 +502,7 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
   cx<T>* spec_t = spec + (long long)nc * g.spec_case;
   {
     const int R = rows_p2(pl, elem);
-    const size_t lds = sizeof(cx<T>) * R * (na1 * (nb1 + 1) + 1);
+    const size_t lds = sizeof(cx<T>) * (R * (na1 * (nb1 + 1) + 1) + (elem == 4 ? na1 * nb1 : 0));
     prof::begin<T>(prof::P2, s);
     hipLaunchKernelGGL(K1.p2f, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, spec_t, tb.tw[1], g,
                        R, rows, st);
@@ -534,7 +534,7 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
   // P4 (P3's tiled copy -> rows of spec)
   {
     const int R = rows_p2(pl, elem);
-    const size_t lds = sizeof(cx<T>) * R * (na1 * (nb1 + 1) + 1);
+    const size_t lds = sizeof(cx<T>) * (R * (na1 * (nb1 + 1) + 1) + (elem == 4 ? na1 * nb1 : 0));
     prof::begin<T>(prof::P4, s);
     hipLaunchKernelGGL(K1.p2i, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, spec_t, tb.tw[1], g,
                        R, rows, st);
