@@ -179,12 +179,12 @@ template <typename T>
 struct Vec16;
 template <>
 struct Vec16<float> {
-  using type = float4;
+  using type = float __attribute__((ext_vector_type(4)));
   static constexpr int n = 4;
 };
 template <>
 struct Vec16<double> {
-  using type = double2;
+  using type = double __attribute__((ext_vector_type(2)));
   static constexpr int n = 2;
 };
 
@@ -233,6 +233,8 @@ __global__ void k_minres_givens(MinresState* st, const double* partials, int np,
 // the slot's xmode schedules (x += cx d_k plus the terms deferred from the two previous iterations).
 // One 16-byte vector per thread over a grid that covers the field once (a grid-stride loop over a
 // fixed grid streamed about 10% slower); every load of the element is issued before its arithmetic.
+// All its loads and stores are nontemporal: nothing reads these lines again before the next
+// iteration's U2, and U2 runs beside P3, whose output P4 partly finds in the memory-side cache.
 // Coefficients come from the slot S2 filled for this iteration (the live state already belongs to
 // the next iteration when U2 runs beside it).
 template <typename T, bool VEC>
@@ -249,25 +251,25 @@ __global__ __launch_bounds__(256) void k_direction(T* d2, const T* d1, const T* 
   const long long nv = n6 / V;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
     if constexpr (VEC) {
-      VT dv = reinterpret_cast<const VT*>(d2 + off)[i];
+      VT dv = __builtin_nontemporal_load(reinterpret_cast<const VT*>(d2 + off) + i);
       const VT d2v = dv;  // d_{k-2}, for a mode-3 solution update
-      const VT uv = reinterpret_cast<const VT*>(uk + off)[i];
-      const VT d1v = reinterpret_cast<const VT*>(d1 + off)[i];
+      const VT uv = __builtin_nontemporal_load(reinterpret_cast<const VT*>(uk + off) + i);
+      const VT d1v = __builtin_nontemporal_load(reinterpret_cast<const VT*>(d1 + off) + i);
       VT xv;
-      if (mode != 0) xv = reinterpret_cast<const VT*>(x + off)[i];
+      if (mode != 0) xv = __builtin_nontemporal_load(reinterpret_cast<const VT*>(x + off) + i);
       T* de = reinterpret_cast<T*>(&dv);
       const T* ue = reinterpret_cast<const T*>(&uv);
       const T* d1e = reinterpret_cast<const T*>(&d1v);
       const T* d2e = reinterpret_cast<const T*>(&d2v);
 #pragma unroll
       for (int e = 0; e < V; ++e) de[e] = a * ue[e] + b * d1e[e] + c * de[e];
-      reinterpret_cast<VT*>(d2 + off)[i] = dv;
+      __builtin_nontemporal_store(dv, reinterpret_cast<VT*>(d2 + off) + i);
       if (mode != 0) {
         T* xe = reinterpret_cast<T*>(&xv);
 #pragma unroll
         for (int e = 0; e < V; ++e)
           xe[e] += (mode == 3 ? xpp * d2e[e] : (T)0) + (mode >= 2 ? xp * d1e[e] : (T)0) + xc * de[e];
-        reinterpret_cast<VT*>(x + off)[i] = xv;
+        __builtin_nontemporal_store(xv, reinterpret_cast<VT*>(x + off) + i);
       }
     } else {
       const T d1s = d1[off + i];
