@@ -21,6 +21,28 @@ __device__ __forceinline__ cx<T> mk(T r, T i) {
   z.im = i;
   return z;
 }
+// Streaming load: the nontemporal hint lets the caches evict the line first.  Used where a pass reads
+// an operand for the last time and its lanes cover whole cache lines (a row's lanes read 128 bytes
+// together); with four-byte lanes, half a line per row and instruction, the hint slowed the passes.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> ld_stream(const cx<T>* p) {
+  using V = T __attribute__((ext_vector_type(2)));
+  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  return mk<T>(v.x, v.y);
+}
+// Streaming only in FP64 (eight-byte lanes, whole lines), an ordinary load in FP32 (four-byte lanes):
+// for the field loads of the axis-2 passes.
+template <typename T>
+__device__ __forceinline__ T ld_stream_wide(const T* p) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
 template <typename T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk<T>(a.re + b.re, a.im + b.im); }
 template <typename T>

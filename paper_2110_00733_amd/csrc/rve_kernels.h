@@ -271,7 +271,7 @@ k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib,
     for (int i = 0; i < NA; ++i) {
       ph[i] = mat.use_phi ? (T)pr[NB * i] : (T)0;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) e[c][i] = xr[c][NB * i];
+      for (int c = 0; c < 6; ++c) e[c][i] = ld_stream_wide(xr[c] + NB * i);
     }
     // element by element, so that e[.][i] is dead once sg[.][i] and its <x, sigma> terms exist
 #pragma unroll
@@ -432,10 +432,10 @@ __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, cx<T>* 
   if (__ballot(oka) != 0) {
     if (S < 0) {
 #pragma unroll
-      for (int i = 0; i < NA; ++i) z[i] = spec[rac * N + t1 + NB * i];
+      for (int i = 0; i < NA; ++i) z[i] = ld_stream(spec + rac * N + t1 + NB * i);
     } else {
 #pragma unroll
-      for (int i = 0; i < NA; ++i) z[i] = tblk[ta + (unsigned)((t1 + NB * i) * g.tile)];
+      for (int i = 0; i < NA; ++i) z[i] = ld_stream(tblk + ta + (unsigned)((t1 + NB * i) * g.tile));
     }
   } else {
 #pragma unroll
@@ -732,7 +732,7 @@ __global__ __launch_bounds__(256) void k_axis0_project(cx<T>* __restrict__ spec,
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) D[c][i] = ok ? base[c * pstride + toff + (long long)i * (NB * g.n1)] : mk<T>(0, 0);
+    for (int i = 0; i < NA; ++i) D[c][i] = ok ? ld_stream(base + c * pstride + toff + (long long)i * (NB * g.n1)) : mk<T>(0, 0);
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
@@ -857,7 +857,7 @@ __global__ __launch_bounds__(512) void k_axis0_project_split(cx<T>* __restrict__
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) D[c][i] = ok ? base[c * pstride + toff + (long long)i * (NB * g.n1)] : mk<T>(0, 0);
+    for (int i = 0; i < NA; ++i) D[c][i] = ok ? ld_stream(base + c * pstride + toff + (long long)i * (NB * g.n1)) : mk<T>(0, 0);
 #pragma unroll
     for (int i = NA; i < E; ++i) D[c][i] = mk<T>(0, 0);
   }
@@ -1078,7 +1078,7 @@ __global__ __launch_bounds__(192) void k_axis0_project_split3(cx<T>* __restrict_
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) D[c][i] = ok ? base[c * pstride + toff + (long long)i * (NB * g.n1)] : mk<T>(0, 0);
+    for (int i = 0; i < NA; ++i) D[c][i] = ok ? ld_stream(base + c * pstride + toff + (long long)i * (NB * g.n1)) : mk<T>(0, 0);
 #pragma unroll
     for (int i = NA; i < E; ++i) D[c][i] = mk<T>(0, 0);
   }
@@ -1196,7 +1196,7 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
       const int k = m + M * l;
 #pragma unroll
       for (int c = 2 * p2; c < 2 * p2 + 2; ++c)
-        sp[c][l] = (n1s < g.n1 && k < g.k2) ? spec[spec_idx(g, cs, k, c, n0, n1s)] : mk<T>(0, 0);
+        sp[c][l] = (n1s < g.n1 && k < g.k2) ? ld_stream(spec + spec_idx(g, cs, k, c, n0, n1s)) : mk<T>(0, 0);
     }
   };
   // Lanczos operands (combination c u_k + c' u_{k-1}) of a pair, fetched early: one pair ahead in
@@ -1216,7 +1216,7 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const long long oo = (2 * p2 + h) * g.nvox + o;
-            dvs[DV_AHEAD ? p2 : 0][j][b][h] = (CB == 1 || a < NA) ? cv * uc[oo] + cvp * umc[oo] : (T)0;
+            dvs[DV_AHEAD ? p2 : 0][j][b][h] = (CB == 1 || a < NA) ? cv * ld_stream_wide(uc + oo) + cvp * ld_stream_wide(umc + oo) : (T)0;
           }
         }
       }
@@ -1241,7 +1241,7 @@ __global__ __launch_bounds__(256) void k_inv_axis2(const cx<T>* __restrict__ spe
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
               const long long oo = (2 * pr + h) * g.nvox + o;
-              dvl[j][b][h] = (CB == 1 || a < NA) ? cv * uc[oo] + cvp * umc[oo] : (T)0;
+              dvl[j][b][h] = (CB == 1 || a < NA) ? cv * ld_stream_wide(uc + oo) + cvp * ld_stream_wide(umc + oo) : (T)0;
             }
           }
         }
