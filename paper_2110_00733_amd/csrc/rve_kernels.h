@@ -240,7 +240,9 @@ k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib,
   if (TWL) {
     for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = tw[i];
   }
-  const int n0 = blockIdx.y;
+  // planes in descending n0: P5 (ascending) wrote the high planes last, so part of them is still in
+  // the memory-side cache when this pass starts
+  const int n0 = g.n0 - 1 - (int)blockIdx.y;
   const int n1_0 = blockIdx.x * W;
   const int tid = threadIdx.x;
   const int t = tid % TT, w = tid / TT;
