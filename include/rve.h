@@ -191,7 +191,8 @@ rve_status rve_apply(const rve_grid* grid, const float* voxel_fraction_field, co
  * recorded on the solve stream; elapsed times are accumulated per kernel kind at the host's
  * convergence checks.  Kinds, in order: P1 stiffness + FFT axis 2 (+ Lanczos alpha), P2 FFT axis 1,
  * P3 FFT axis 0 + projection + inverse, P4 inverse FFT axis 1, P5 inverse FFT axis 2 + Lanczos
- * update, S1 Lanczos alpha, S2 Givens step, U2 direction + solution update; kinds 0-7 count these
+ * update, S1 Lanczos alpha (now computed by extra blocks of P2, so this kind records no launches
+ * and P2's time includes it), S2 Givens step, U2 direction + solution update; kinds 0-7 count these
  * passes on FP32 fields, kinds 8-15 (names ending in _f64) the same passes on FP64 fields.
  * rve_profile_read fills total milliseconds and launch counts for up to max_kinds kinds and
  * returns the number of kinds (16).  Profiled solves launch their kernels directly (no graph

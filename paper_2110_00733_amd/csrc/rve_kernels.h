@@ -161,6 +161,47 @@ __device__ __forceinline__ void alpha_step(MinresState& S, double sum) {
   S.cu_vp = S.beta * S.ib_prev;
 }
 
+// S1: alpha_k from the P1 partials of case cs; a case whose previous iteration finished is retired
+// instead (that iteration's U2 has run by now).  Run by extra blocks of P2 (the pass after P1, which
+// reads none of what this writes), so that it needs no launch of its own.  The partials are summed in
+// the order a 256-thread block sums them (eight loads in flight per thread; per wave the shuffle
+// tree, whose lane 0 adds the upper half onto the lower one at halving distances; the four wave sums
+// in turn), whatever the size of the block that runs it, which may be below one wave; vsum holds 256
+// doubles of LDS.
+__device__ void minres_alpha_block(MinresState* st, const double* partials, int np, int cs, double* vsum) {
+  MinresState& S = st[cs];
+  if (S.done) return;
+  if (S.finish) {
+    if (threadIdx.x == 0) S.done = 1;
+    return;
+  }
+  constexpr int VT = 256;
+  const double* p = partials + (long long)cs * np;
+  for (int v = threadIdx.x; v < VT; v += blockDim.x) {
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = v;
+    for (; i + 7 * VT < np; i += 8 * VT) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += p[i + u * VT];
+    }
+    for (; i < np; i += VT) a[0] += p[i];
+    vsum[v] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  }
+  __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) {
+    for (int q = threadIdx.x; q < (VT / 64) * off; q += blockDim.x) {
+      const int l = (q / off) * 64 + q % off;  // lane q % off of virtual wave q / off
+      vsum[l] += vsum[l + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < VT / 64; ++w) sum += vsum[w * 64];
+    alpha_step(S, sum);
+  }
+}
+
 // beta_{k+1} = ||u_{k+1}||; Givens QR step of the extended tridiagonal matrix; residual recurrence
 // |phibar|; coefficients of d_k = (v_k - delta_k d_{k-1} - eps_k d_{k-2}) / gamma_k and x += tau d_k.
 __device__ __forceinline__ void givens_step(MinresState& S, double sumsq) {
@@ -377,12 +418,18 @@ k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib,
 template <typename T, int NA, int NB, int S>
 __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, cx<T>* __restrict__ spec_t,
                                                const cx<T>* __restrict__ tw, GridDims g, int R, long long total_rows,
-                                               const MinresState* __restrict__ st) {
+                                               const MinresState* __restrict__ st, MinresState* s1_st,
+                                               const double* s1_partials, int s1_np, int s1_blocks) {
   constexpr int N = NA * NB;
   constexpr int TT = NB;
   constexpr int CB = (NA + TT - 1) / TT;
   constexpr int RSW = NA * (NB + 1) + 1;  // LDS words (complex) per row: odd, so rows fall on distinct banks
   extern __shared__ unsigned char smem_raw[];
+  // MINRES iterations: the first s1_blocks blocks (one per load case) run S1 and nothing else
+  if ((int)blockIdx.x < s1_blocks) {
+    minres_alpha_block(s1_st, s1_partials, s1_np, (int)blockIdx.x, reinterpret_cast<double*>(smem_raw));
+    return;
+  }
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x;
   // FP32: the stage twiddles come from a copy of the table in LDS behind the rows' exchange areas,
@@ -392,7 +439,7 @@ __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, cx<T>* 
   if (TWL) {
     for (int i = tid; i < N; i += blockDim.x) twl[i] = tw[i];
   }
-  const long long row0 = (long long)blockIdx.x * R;
+  const long long row0 = ((long long)blockIdx.x - s1_blocks) * R;
   const int t_row = tid % TT, w_row = tid / TT;  // element index fastest
   const int w_til = tid % R, t_til = tid / R;    // row index fastest
   const int t1 = (S < 0) ? t_row : t_til, w1 = (S < 0) ? w_row : w_til;  // stage A (input side)

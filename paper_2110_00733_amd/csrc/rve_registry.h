@@ -8,7 +8,8 @@ template <typename T>
 using P1Fn = void (*)(const T*, const double*, int, const float*, Material<T>, cx<T>*, const cx<T>*, GridDims, int,
                       const MinresState*, double*);
 template <typename T>
-using P2Fn = void (*)(cx<T>*, cx<T>*, const cx<T>*, GridDims, int, long long, const MinresState*);
+using P2Fn = void (*)(cx<T>*, cx<T>*, const cx<T>*, GridDims, int, long long, const MinresState*, MinresState*,
+                      const double*, int, int);
 template <typename T>
 using P3Fn = void (*)(cx<T>*, const cx<T>*, FreqTables<T>, GridDims, int, T, const MinresState*);
 template <typename T>

@@ -1,8 +1,8 @@
 // Host driver and Krylov kernels of the gfx950 Galerkin-FFT homogenization solver (C ABI in rve.h).
 //
-// One MINRES iteration is eight launches, no host involvement:
-//   P1 stiffness + FFT axis 2, with per-block partials of alpha = <v, C v>;  S1 alpha (one block)
-//   P2, P3 (projection), P4 transforms
+// One MINRES iteration is seven launches, no host involvement:
+//   P1 stiffness + FFT axis 2, with per-block partials of alpha = <v, C v>
+//   P2, P3 (projection), P4 transforms; S1 (alpha from P1's partials) runs in extra blocks of P2
 //   P5 inverse FFT axis 2 fused with the Lanczos three-term update and ||u_{k+1}||^2 partials
 //   S2 Givens QR step + convergence test (one block);  U2 search direction + solution update, on a
 //   second stream beside the next iteration's P3 (see U2Side).
@@ -482,6 +482,7 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
   }
   const int N2 = g.n2;
   const int elem = (int)sizeof(T);
+  int s1_np = 0;  // P1 blocks (alpha partials per case), summed by S1 inside P2
   // P1
   {
     const int W = tile_p1(pl, elem);
@@ -491,21 +492,20 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     hipLaunchKernelGGL(mat.tan ? K2.p1t : K2.p1, grid, dim3(W * nb2), lds, s, x, xscale, (int)(sizeof(MinresState) / sizeof(double)),
                        phi, mat, spec, tb.tw[2], g, W, st, uk ? partials : nullptr);
     prof::end(s);
-    if (uk) {
-      prof::begin<T>(prof::S1, s);
-      hipLaunchKernelGGL(k_minres_alpha, dim3(nc), dim3(256), 0, s, st, partials, (int)(grid.x * grid.y));
-    }
-    prof::end(s);
+    s1_np = (int)(grid.x * grid.y);
   }
   // P2 (rows of spec -> P3's tiled copy, the second half of the spectrum buffer)
   const long long rows = (long long)nc * g.k2 * 6 * g.n0;
   cx<T>* spec_t = spec + (long long)nc * g.spec_case;
   {
     const int R = rows_p2(pl, elem);
-    const size_t lds = sizeof(cx<T>) * (R * (na1 * (nb1 + 1) + 1) + (elem == 4 ? na1 * nb1 : 0));
+    // in MINRES iterations P2's first nc blocks run S1 (alpha_k from P1's partials), in 256 doubles of LDS
+    const int s1b = uk ? nc : 0;
+    const size_t lds = std::max<size_t>(sizeof(cx<T>) * (R * (na1 * (nb1 + 1) + 1) + (elem == 4 ? na1 * nb1 : 0)),
+                                        s1b ? 256 * sizeof(double) : 0);
     prof::begin<T>(prof::P2, s);
-    hipLaunchKernelGGL(K1.p2f, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, spec_t, tb.tw[1], g,
-                       R, rows, st);
+    hipLaunchKernelGGL(K1.p2f, dim3((unsigned)((rows + R - 1) / R + s1b)), dim3(R * nb1), lds, s, spec, spec_t,
+                       tb.tw[1], g, R, rows, st, uk ? st : nullptr, uk ? partials : nullptr, s1_np, s1b);
     prof::end(s);
     if (after_p2) (void)hipEventRecord(after_p2, s);
   }
@@ -537,7 +537,7 @@ static void apply_op(const Plan& pl, int nc, const T* x, const double* xscale, c
     const size_t lds = sizeof(cx<T>) * (R * (na1 * (nb1 + 1) + 1) + (elem == 4 ? na1 * nb1 : 0));
     prof::begin<T>(prof::P4, s);
     hipLaunchKernelGGL(K1.p2i, dim3((unsigned)((rows + R - 1) / R)), dim3(R * nb1), lds, s, spec, spec_t, tb.tw[1], g,
-                       R, rows, st);
+                       R, rows, st, (MinresState*)nullptr, (const double*)nullptr, 0, 0);
     prof::end(s);
   }
   // P5

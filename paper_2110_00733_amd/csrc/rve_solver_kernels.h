@@ -188,22 +188,6 @@ struct Vec16<double> {
   static constexpr int n = 2;
 };
 
-// S1: alpha_k from the P1 partials (fixed-order sum).  Also retires a case whose previous iteration
-// finished (that iteration's U2 has run by now).
-__global__ void k_minres_alpha(MinresState* st, const double* partials, int np) {
-  __shared__ double red[16];
-  const int cs = blockIdx.x;
-  MinresState& S = st[cs];
-  if (S.done) return;
-  if (S.finish) {
-    __syncthreads();
-    if (threadIdx.x == 0) S.done = 1;
-    return;
-  }
-  const double s = sum_partials(partials + (long long)cs * np, np, red);
-  if (threadIdx.x == 0) alpha_step(S, s);
-}
-
 // S2: beta_{k+1} from the P5 partials, Givens step, convergence test; the iteration's U2
 // coefficients go to slot `slot` (inactive when the case had already finished).
 __global__ void k_minres_givens(MinresState* st, const double* partials, int np, int slot) {
