@@ -630,6 +630,31 @@ def _force_tiles(rve, n, elem, W1, W3, R2, S3, path):
     assert rve.load_tuning(str(path)) == 1
 
 
+def test_alpha_sum_independent_of_p2_block(tmp_path):
+    """The Lanczos alpha is summed from P1's partials by extra blocks of P2, in one fixed order for any
+    P2 block size: with one row per P2 block (blocks of a few threads, below one wave) a solve repeats
+    the default tiles' iterates bit for bit, in both precisions (the operator itself does not depend on
+    P2's rows per block)."""
+    rve = _rve()
+    n = (20, 12, 16)
+    phi, _ = li.octet_phase_map(n, 0.2)
+    d = _dev(phi)
+    E = np.eye(6)[[0, 4]]
+    for prec, elem in ((rve.FP64, 8), (rve.FP32_MIXED, 4)):
+        t0 = rve.tuned_tiles(n, prec)[0]
+        assert t0[2] > 1
+        ref = rve.solve(d, C1, E, precision=prec, tol=1e-8)
+        try:
+            _force_tiles(rve, n, elem, t0[0], t0[1], 1, t0[3], tmp_path / f"t{elem}.jsonl")
+            assert rve.tuned_tiles(n, prec)[0][2] == 1
+            out = rve.solve(d, C1, E, precision=prec, tol=1e-8)
+        finally:
+            _force_tiles(rve, n, elem, t0[0], t0[1], t0[2], t0[3], tmp_path / f"r{elem}.jsonl")
+        assert ref["status"] == 0 and out["status"] == 0
+        assert np.array_equal(out["iterations"], ref["iterations"])
+        assert np.array_equal(out["eff_stress"], ref["eff_stress"])
+
+
 # tiles the autotuner keeps at 256^3: P1/P5 16 rows, P3 4 or 8 pencils (two-way split in FP32, three
 # one-wave groups in FP64), P2/P4 8 or 16 rows
 TILES_256 = {"f32": [(16, 4, 8, 2), (16, 8, 16, 2)], "f64": [(16, 4, 8, 3), (16, 4, 16, 2)]}
