@@ -34,6 +34,14 @@ __device__ __forceinline__ cx<T> ld_stream(const cx<T>* p) {
   const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
   return mk<T>(v.x, v.y);
 }
+template <typename T>
+__device__ __forceinline__ void st_stream(cx<T>* p, cx<T> z) {
+  using V = T __attribute__((ext_vector_type(2)));
+  V v;
+  v.x = z.re;
+  v.y = z.im;
+  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+}
 // Streaming only in FP64 (eight-byte lanes, whole lines), an ordinary load in FP32 (four-byte lanes):
 // for the field loads of the axis-2 passes.
 template <typename T>

@@ -517,7 +517,7 @@ __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, cx<T>* 
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           if (S > 0)
-            spec[rb * N + a + NA * b] = yb[b];
+            st_stream(spec + rb * N + a + NA * b, yb[b]);
           else
             tblk_w[tb + (unsigned)((a + NA * b) * g.tile)] = yb[b];
         }
