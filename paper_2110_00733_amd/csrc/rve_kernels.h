@@ -395,8 +395,8 @@ k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib,
         const cx<T> Zm = lds[ws * (N + 1) + (N - k) % N];
         const cx<T> A = mk<T>((Z.re + Zm.re) * (T)0.5, (Z.im - Zm.im) * (T)0.5);
         const cx<T> B = mk<T>((Z.im + Zm.im) * (T)0.5, (Zm.re - Z.re) * (T)0.5);
-        spec[spec_idx(g, cs, k, 2 * pr, n0, n1s)] = A;
-        spec[spec_idx(g, cs, k, 2 * pr + 1, n0, n1s)] = B;
+        st_stream(spec + spec_idx(g, cs, k, 2 * pr, n0, n1s), A);
+        st_stream(spec + spec_idx(g, cs, k, 2 * pr + 1, n0, n1s), B);
       }
     }
   }
