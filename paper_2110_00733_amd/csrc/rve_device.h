@@ -34,6 +34,8 @@ __device__ __forceinline__ cx<T> ld_stream(const cx<T>* p) {
   const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
   return mk<T>(v.x, v.y);
 }
+// Streaming store: the line goes to HBM while the writer runs instead of being written back from the
+// caches while the next pass streams its own operands.
 template <typename T>
 __device__ __forceinline__ void st_stream(cx<T>* p, cx<T> z) {
   using V = T __attribute__((ext_vector_type(2)));

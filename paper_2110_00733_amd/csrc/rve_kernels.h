@@ -395,6 +395,7 @@ k_fwd_axis2(const T* __restrict__ x, const double* __restrict__ xscale_ib,
         const cx<T> Zm = lds[ws * (N + 1) + (N - k) % N];
         const cx<T> A = mk<T>((Z.re + Zm.re) * (T)0.5, (Z.im - Zm.im) * (T)0.5);
         const cx<T> B = mk<T>((Z.im + Zm.im) * (T)0.5, (Zm.re - Z.re) * (T)0.5);
+        // streaming stores: slower here, but P2 then reads without this pass's write-backs beside it
         st_stream(spec + spec_idx(g, cs, k, 2 * pr, n0, n1s), A);
         st_stream(spec + spec_idx(g, cs, k, 2 * pr + 1, n0, n1s), B);
       }
@@ -516,7 +517,7 @@ __global__ __launch_bounds__(256) void k_axis1(cx<T>* __restrict__ spec, cx<T>* 
       if (okb) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          if (S > 0)
+          if (S > 0)  // streaming stores: P5's gather then runs without P4's write-backs beside it
             st_stream(spec + rb * N + a + NA * b, yb[b]);
           else
             tblk_w[tb + (unsigned)((a + NA * b) * g.tile)] = yb[b];
